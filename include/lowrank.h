@@ -1,0 +1,209 @@
+/*
+ * lowrank.h -- C ABI of the MI355X (gfx950) low-rank approximation library.
+ *
+ * The library computes an orthonormal U_k (d x k) whose projector
+ * Pi = U_k U_k^T approximately minimises ||X - Pi X||_F for a d x n matrix X
+ * (problem statement, Section 1 of Gonen & Shalev-Shwartz, "Faster Low-rank
+ * Approximation using Adaptive Gap-based Preconditioning").  The method is the
+ * q = k branch of the paper's Algorithm "main" (Section 3.2): block power
+ * iteration with oversampling (d x p block, k < p) on the shift-and-invert
+ * operator (lambda I - XX^T)^{-1} (Section 1, item 2; Algorithm "subspace
+ * iteration", Section 2.2.1), every product with that operator computed by a
+ * minibatch SVRG solver (Section 2.3, Theorem "svrgSolve"), the shift set by
+ * Algorithm "shiftTune" (Appendix B), and a final Rayleigh-Ritz step
+ * (Algorithm "second stage", Section 2.2.2).
+ *
+ * Conventions
+ *   - X is d x n with data points as columns (Section 1).  Dense X is stored
+ *     column-major: element (r, i) at values[i * ld + r], ld >= d.
+ *   - All matrix pointers passed to the library are DEVICE pointers unless a
+ *     parameter says "host".  d x p blocks are FP64, column-major, leading
+ *     dimension d.
+ *   - Every call returns lr_status; LR_OK is 0.  lowrank_last_error() gives a
+ *     human-readable message for the last failing call on this thread.
+ *   - No C++ type or exception crosses this boundary.
+ *
+ * Ownership
+ *   - The caller owns X, U_out and every other buffer it passes.  X must stay
+ *     valid and unchanged between lowrank_plan and the end of lowrank_solve.
+ *   - A plan owns its device workspace, allocated in lowrank_plan and released
+ *     in lowrank_destroy; lowrank_solve allocates nothing.
+ *   - A plan is not thread-safe.  Separate plans on separate streams may run
+ *     concurrently.  All work of a plan is enqueued on the stream given to
+ *     lowrank_plan; calls return after the results they report are complete.
+ */
+#ifndef LOWRANK_H
+#define LOWRANK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LR_MAX_P 64          /* largest block width p supported */
+#define LR_MAX_SHIFT_ROUNDS 64
+
+typedef enum {
+  LR_OK = 0,
+  LR_EINVAL = 1,    /* bad argument: sizes (need 1 <= k < p < d, p <= n, p <= LR_MAX_P),
+                       null pointer, unsupported dtype/layout, or NaN/Inf in X */
+  LR_ENOMEM = 2,    /* device allocation failed */
+  LR_ENOGAP = 3,    /* estimated gap budget theta_k - theta_p is numerically zero
+                       (the paper assumes sigma_k > sigma_{p+1}, Theorem "mainResult") */
+  LR_ENOCONV = 4,   /* an inner solve hit max_epochs, or the outer loop hit max_outer
+                       (U_out is still written in the latter case) */
+  LR_ESHIFT = 5,    /* the inner solver diverged or the shift estimate was not
+                       positive: lambda not above lambda_1; or shift tuning did not
+                       reach the interval of eq. (shiftClose) within max_shift_rounds */
+  LR_ENOTSPD = 6,   /* Cholesky-QR met a Gram matrix that is not positive definite
+                       (block lost rank) */
+  LR_EDEVICE = 7,   /* a HIP runtime call or kernel launch failed */
+  LR_EBUSY = 8
+} lr_status;
+
+typedef enum { LR_F64 = 0, LR_F32 = 1, LR_BF16 = 2 } lr_dtype;
+typedef enum { LR_DENSE_COLMAJOR = 0, LR_CSC = 1 } lr_layout;
+
+/* The input matrix.  values: device pointer to d x n elements of `dtype`
+ * (BF16 as raw uint16 bit patterns).  Only LR_DENSE_COLMAJOR is implemented;
+ * col_ptr, row_idx and nnz are reserved for the compressed-column layout. */
+typedef struct lr_matrix {
+  int64_t d, n, ld, nnz;
+  int32_t dtype;          /* lr_dtype */
+  int32_t layout;         /* lr_layout */
+  const void* values;
+  const int32_t* col_ptr;
+  const int32_t* row_idx;
+} lr_matrix;
+
+/* The decisions a solve took (or, for replay, is told to take).
+ *   lambda       shift used by every shift-and-invert solve
+ *   mu_hat       estimate of lambda - lambda_1 used to size the inner solver
+ *   delta_hat    gap budget estimate (theta_k - theta_p) / 1.5 (Section 3)
+ *   eta, m, b    inner solver step size, steps per epoch, minibatch size
+ *   tau          relative residual at which an inner solve stops
+ *   eps_stop     outer stopping threshold eps / (k mu_F)
+ *   first_solve  solve index of the first shift-and-invert solve (= number of
+ *                shift-tuning rounds); solve indices key the sampling streams
+ *   outer        number of outer iterations L
+ *   epochs       host array, epochs of each of the `outer` solves.  For
+ *                lowrank_get_schedule the caller provides it with capacity
+ *                n_epochs (entries beyond capacity are dropped); for replay it
+ *                must hold `outer` entries. */
+typedef struct lr_schedule {
+  double lambda, mu_hat, delta_hat, eta, tau, eps_stop;
+  int64_t m, b;
+  int32_t first_solve, outer;
+  int32_t n_epochs;
+  int32_t* epochs;
+} lr_schedule;
+
+/* Options.  Fill with lowrank_options_default, then override.
+ *   seed            64-bit key of every Philox stream (initial blocks, samples)
+ *   shift_mode      0: lambda0 = theta_1 + ||r_1|| + Delta/10 ; 1: 1.5 theta_1
+ *                   (the literal start of Algorithm "shiftTune")
+ *   est_iters       plain subspace-iteration steps of the estimate phase (4)
+ *   max_outer, max_epochs, max_shift_rounds: iteration caps (2000, 60, 30)
+ *   polish          plain FP64 power steps before the final Rayleigh-Ritz (0)
+ *   batch           minibatch size b; 0 = automatic
+ *   eta_scale       multiplies the automatic step size (1.0)
+ *   tau_shift       inner-solve tolerance during shift tuning (1e-2)
+ *   replay          NULL, or a schedule to follow instead of estimating the
+ *                   shift and deciding when to stop (lambda, mu_hat, eta, m, b,
+ *                   first_solve, outer and epochs are used)
+ *   timing          1: record HIP events around passes and inner-step loops
+ *                   and report their durations in lr_report */
+typedef struct lr_options {
+  uint64_t seed;
+  int32_t shift_mode;
+  int32_t est_iters, max_outer, max_epochs, max_shift_rounds, polish;
+  int64_t batch;
+  double eta_scale, tau_shift;
+  const lr_schedule* replay;
+  int32_t timing;
+} lr_options;
+
+/* What a solve did.  Host struct filled by lowrank_solve. */
+typedef struct lr_report {
+  double theta_est[LR_MAX_P];     /* estimate-phase Ritz values of XX^T, descending */
+  double res_est[LR_MAX_P];       /* their residual norms ||A s_i - theta_i s_i|| */
+  double fro2;                    /* ||X||_F^2 */
+  double mu_F;                    /* ||X||_F / sqrt(||X||_F^2 - sum_{i<=k} theta_i) */
+  int32_t shift_rounds;
+  double shift_lambda[LR_MAX_SHIFT_ROUNDS];   /* lambda tried in each round */
+  double shift_gap[LR_MAX_SHIFT_ROUNDS];      /* its estimate 1/nu_1 of lambda - lambda_1 */
+  int32_t outer;
+  int64_t total_epochs, passes, steps;
+  double last_change;             /* last outer-iteration subspace change */
+  double ms_pass_total;           /* timing = 1: summed duration of all passes */
+  double ms_steps_total;          /* timing = 1: summed duration of all inner-step loops */
+  int64_t timed_passes, timed_steps;
+} lr_report;
+
+typedef struct lr_plan_s* lr_plan;
+
+const char* lowrank_status_string(lr_status s);
+const char* lowrank_last_error(void);
+void lowrank_options_default(lr_options* opt);
+
+/* Validate sizes and allocate the plan's workspace on the current device.
+ * hip_stream: a hipStream_t (NULL = default stream).  Fails with LR_EINVAL on
+ * bad sizes or pointers, LR_ENOMEM if the workspace cannot be allocated. */
+lr_status lowrank_plan(lr_plan* out, const lr_matrix* X, int k, int p, double eps,
+                       const lr_options* opt, void* hip_stream);
+
+/* Run the whole method on the plan's X.
+ *   U_out      device, d x k FP64 column-major: orthonormal U_k, each column's
+ *              largest-magnitude entry positive (may be NULL)
+ *   theta_out  host, k FP64: Ritz values sigma_hat_i^2, descending (may be NULL)
+ *   rep        host report (may be NULL) */
+lr_status lowrank_solve(lr_plan plan, double* U_out, double* theta_out, lr_report* rep);
+
+/* Copy the schedule of the last solve.  out->epochs / out->n_epochs give a
+ * caller-owned host buffer and its capacity (may be NULL / 0). */
+lr_status lowrank_get_schedule(lr_plan plan, lr_schedule* out);
+
+void lowrank_destroy(lr_plan plan);
+
+/* ---- Single steps of the path, on a plan's X and stream (for testing and
+ * measurement).  All matrices FP64 device, column-major, leading dim d. ---- */
+
+/* Y = X (X^T W) for a d x ncols block W (ncols <= p); A = XX^T is never
+ * formed (Section 2.2.1, footnote). */
+lr_status lowrank_op_apply_A(lr_plan plan, const double* W, double* Y, int ncols);
+
+/* Plan step a0: column squared norms w (n), quantised cumulative table
+ * cdf (n+1, uint64), ||X||_F^2 (host). */
+lr_status lowrank_op_prepare(lr_plan plan, double* w_out, uint64_t* cdf_out, double* fro2_out);
+
+/* The b column indices and weights 1/(b pi_i) of inner step `step` of epoch
+ * `epoch` of solve `solve` (requires lowrank_op_prepare or a solve first). */
+lr_status lowrank_op_sample(lr_plan plan, int32_t solve, int32_t epoch, int32_t step, int64_t b,
+                            int32_t* idx_out, double* scale_out);
+
+/* d x p' Gaussian block of stream `tag` (1 estimate, 2 shift-and-invert) and
+ * solve index `solve`, as used for the random start of the subspace
+ * iteration (Algorithm "subspace iteration", Section 2.2.1). */
+lr_status lowrank_op_gaussian(lr_plan plan, int32_t tag, int32_t solve, int ncols, double* S_out);
+
+/* S = W R^{-1} with R the Cholesky factor of W^T W, applied twice. */
+lr_status lowrank_op_cholqr2(lr_plan plan, const double* W, double* S_out, int ncols);
+
+/* Symmetric eigendecomposition of an m x m matrix (m <= LR_MAX_P), descending,
+ * eigenvector columns with their largest-magnitude entry positive. */
+lr_status lowrank_op_eigh(lr_plan plan, const double* H, int m, double* vals_out,
+                          double* vecs_out);
+
+/* One inner solve of (lambda I - XX^T) W = S with a fixed number of epochs
+ * (requires lowrank_op_prepare or a solve first).  res_out: host, epochs+1
+ * residual norms ||G~||_F (may be NULL). */
+lr_status lowrank_op_svrg_solve(lr_plan plan, const double* S, double lambda, double eta,
+                                int64_t m, int64_t b, int32_t solve, int32_t epochs,
+                                double* W_out, double* res_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOWRANK_H */

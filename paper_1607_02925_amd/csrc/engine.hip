@@ -1,0 +1,631 @@
+// Host engine of the shift-and-invert low-rank path and the C ABI of
+// lowrank.h.  The engine only sequences device kernels and takes the scalar
+// decisions of the method (gap budget, shift, inner-solver constants, stopping)
+// from small device-to-host copies; every step over X or a d x p block runs
+// on the GPU.
+#include "lowrank.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+lr_status fail(lr_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define LR_HIP(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(LR_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define LR_CHECK(expr)              \
+  do {                              \
+    lr_status s_ = (expr);          \
+    if (s_ != LR_OK) return s_;     \
+  } while (0)
+
+constexpr uint32_t TAG_EST_INIT = 1, TAG_SI_INIT = 2, TAG_SAMPLES = 3;
+
+inline uint32_t stream_word(uint32_t tag, uint32_t solve) { return (tag << 28) | solve; }
+
+}  // namespace
+
+struct lr_plan_s {
+  hipStream_t st = nullptr;
+  lr::XView X{};
+  int k = 0, p = 0;
+  double eps = 0;
+  lr_options opt{};
+  bool replay = false;
+  lr_schedule rsched{};
+  std::vector<int32_t> repochs;
+  int64_t d = 0, n = 0, bmax = 0;
+
+  std::vector<void*> allocs;
+  double *w = nullptr, *S = nullptr, *W = nullptr, *Wt = nullptr, *G = nullptr, *Y = nullptr;
+  double *Dl = nullptr, *Tm1 = nullptr, *Tm2 = nullptr, *Sest = nullptr, *V = nullptr;
+  double *Vprev = nullptr, *T = nullptr, *Ypart = nullptr, *C = nullptr, *scale = nullptr;
+  double *part = nullptr, *scratch = nullptr;
+  double *H = nullptr, *Q = nullptr, *vals = nullptr, *M = nullptr, *Rinv = nullptr;
+  double *kk1 = nullptr, *kk2 = nullptr, *res = nullptr, *dfro2 = nullptr, *dnorm = nullptr;
+  uint64_t* cdf = nullptr;
+  int32_t* idx = nullptr;
+  int *dinfo = nullptr, *dbad = nullptr;
+  double* hpin = nullptr;
+  lr::PassBufs pb{};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+  bool prepared = false;
+  double fro2 = 0;
+  lr_schedule sched{};
+  std::vector<int32_t> epochs;
+  lr_report rep{};
+
+  ~lr_plan_s() {
+    for (void* a : allocs) (void)hipFree(a);
+    if (hpin) (void)hipHostFree(hpin);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+
+  template <typename Tp>
+  lr_status alloc(Tp** out, size_t count) {
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, std::max<size_t>(count, 1) * sizeof(Tp)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LR_ENOMEM, "device allocation failed");
+    }
+    allocs.push_back(ptr);
+    *out = (Tp*)ptr;
+    return LR_OK;
+  }
+
+  // Copy `bytes` from device to host (synchronises the stream).
+  lr_status read(void* host, const void* dev, size_t bytes) {
+    LR_HIP(hipMemcpyAsync(hpin, dev, bytes, hipMemcpyDeviceToHost, st));
+    LR_HIP(hipStreamSynchronize(st));
+    std::memcpy(host, hpin, bytes);
+    return LR_OK;
+  }
+
+  lr_status check_spd() {
+    int info = 0;
+    LR_CHECK(read(&info, dinfo, sizeof(int)));
+    if (info) return fail(LR_ENOTSPD, "Cholesky-QR: Gram matrix not positive definite");
+    return LR_OK;
+  }
+
+  // Y = alpha X (X^T W) + beta A + gamma B   (W: d x ncols)
+  lr_status applyA(const double* Win, double* Yout, int ncols, double alpha = 1.0,
+                   const double* A = nullptr, double beta = 0.0, const double* B = nullptr,
+                   double gamma = 0.0) {
+    LR_HIP(lr::pass_xtw(X, Win, ncols, T, st));
+    LR_HIP(lr::pass_xt(X, T, ncols, pb, alpha, A, beta, B, gamma, Yout, st));
+    rep.passes++;
+    return LR_OK;
+  }
+
+  lr_status gram_dd(const double* A, int pa, const double* B, int pb_, double* out) {
+    LR_HIP(lr::gram(A, 1, d, pa, B, 1, d, pb_, d, part, out, st));
+    return LR_OK;
+  }
+
+  // S = W R^{-1}, twice (Cholesky-QR2).  Win may equal Sout.
+  lr_status cholqr2(const double* Win, double* Sout, int ncols) {
+    LR_CHECK(gram_dd(Win, ncols, Win, ncols, H));
+    LR_HIP(lr::chol_rinv(H, ncols, Rinv, dinfo, st));
+    LR_HIP(lr::gemm_small(d, ncols, ncols, Win, Rinv, ncols, Tm1, 0.0, nullptr, st));
+    LR_CHECK(gram_dd(Tm1, ncols, Tm1, ncols, H));
+    LR_HIP(lr::chol_rinv(H, ncols, Rinv, dinfo, st));
+    LR_HIP(lr::gemm_small(d, ncols, ncols, Tm1, Rinv, ncols, Sout, 0.0, nullptr, st));
+    return LR_OK;
+  }
+
+  lr_status prepare() {
+    LR_HIP(hipMemsetAsync(dbad, 0, sizeof(int), st));
+    LR_HIP(lr::colnorms(X, w, dbad, st));
+    int bad = 0;
+    LR_CHECK(read(&bad, dbad, sizeof(int)));
+    if (bad) return fail(LR_EINVAL, "non-finite entries in X");
+    LR_HIP(lr::build_table(w, n, cdf, dfro2, scratch, st));
+    LR_CHECK(read(&fro2, dfro2, sizeof(double)));
+    if (!(fro2 > 0)) return fail(LR_EINVAL, "X is zero");
+    prepared = true;
+    return LR_OK;
+  }
+
+  void constants(double theta1, double lam, double mu, int64_t* b, double* eta, int64_t* m) const {
+    int64_t bb;
+    if (opt.batch > 0) {
+      bb = opt.batch;
+    } else {
+      const double bstar = 4.0 * fro2 * theta1 / (lam * mu);
+      const double l2 = std::ceil(std::log2(std::max(bstar, 1.0)));
+      bb = (int64_t)1 << (int64_t)std::max(0.0, l2);
+      bb = std::min<int64_t>(std::max<int64_t>(bb, 256), 8192);
+    }
+    bb = std::min(bb, n);
+    const double sig2 = fro2 * theta1 / (double)bb;
+    *eta = opt.eta_scale * std::min(1.0 / lam, mu / (4.0 * sig2));
+    *m = (int64_t)std::ceil(2.0 / (*eta * mu));
+    *b = bb;
+  }
+
+  // Inner solve of (lam I - XX^T) W = Srhs; the result is left in Wt.
+  lr_status svrg_solve(const double* Srhs, double lam, double eta, int64_t m, int64_t b,
+                       int32_t solve, double tau, int32_t fixed_epochs, int32_t* epochs_out,
+                       std::vector<double>* hist) {
+    if (b > bmax) return fail(LR_EINVAL, "minibatch larger than the plan's workspace");
+    const int64_t cnt = d * p;
+    // warm start W0 = S (lam I - S^T A S)^{-1}; its gradient costs no extra pass
+    LR_CHECK(applyA(Srhs, Y, p));
+    LR_CHECK(gram_dd(Srhs, p, Y, p, H));
+    LR_HIP(lr::eigh(H, p, vals, Q, st));
+    LR_HIP(lr::shift_inverse(vals, Q, p, lam, M, st));
+    LR_HIP(lr::gemm_small(d, p, p, Srhs, M, p, Wt, 0.0, nullptr, st));
+    LR_HIP(lr::lincomb(cnt, lam, Srhs, -1.0, Y, 0.0, nullptr, Tm1, st));
+    LR_HIP(lr::gemm_small(d, p, p, Tm1, M, p, G, -1.0, Srhs, st));
+    LR_HIP(lr::sumsq(Srhs, cnt, part, dnorm, st));
+    LR_HIP(lr::sumsq(G, cnt, part, dnorm + 1, st));
+    double nr[2];
+    LR_CHECK(read(nr, dnorm, 2 * sizeof(double)));
+    const double sn = std::sqrt(nr[0]);
+    const double r0 = std::sqrt(nr[1]);
+    double r = r0;
+    if (hist) hist->push_back(r);
+    const uint32_t w3 = stream_word(TAG_SAMPLES, (uint32_t)solve);
+    int32_t e = 0;
+    for (;;) {
+      if (fixed_epochs < 0) {
+        if (r <= tau * sn) break;
+        if (e >= opt.max_epochs) return fail(LR_ENOCONV, "inner solver did not converge");
+      } else if (e >= fixed_epochs) {
+        break;
+      }
+      LR_HIP(hipMemsetAsync(Dl, 0, cnt * sizeof(double), st));
+      if (opt.timing) LR_HIP(hipEventRecord(ev[0], st));
+      for (int64_t t = 0; t < m; ++t) {
+        LR_HIP(lr::step_sample_dot(X, p, cdf, opt.seed, (uint32_t)t, (uint32_t)e, w3, b, Dl, idx,
+                                   scale, C, st));
+        LR_HIP(lr::step_update(X, p, b, idx, C, G, Dl, lam, eta, st));
+      }
+      if (opt.timing) LR_HIP(hipEventRecord(ev[1], st));
+      rep.steps += m;
+      LR_HIP(lr::lincomb(cnt, 1.0, Wt, 1.0, Dl, 0.0, nullptr, Wt, st));
+      if (opt.timing) LR_HIP(hipEventRecord(ev[2], st));
+      LR_CHECK(applyA(Wt, G, p, -1.0, Wt, lam, Srhs, -1.0));
+      if (opt.timing) LR_HIP(hipEventRecord(ev[3], st));
+      LR_HIP(lr::sumsq(G, cnt, part, dnorm, st));
+      LR_CHECK(read(&r, dnorm, sizeof(double)));
+      r = std::sqrt(r);
+      if (opt.timing) {
+        float ms = 0;
+        LR_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        rep.ms_steps_total += ms;
+        rep.timed_steps += m;
+        LR_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+        rep.ms_pass_total += ms;
+        rep.timed_passes += 1;
+      }
+      ++e;
+      if (hist) hist->push_back(r);
+      if (!std::isfinite(r) || r > 1e3 * r0)
+        return fail(LR_ESHIFT, "inner solver diverged: shift not above lambda_1");
+    }
+    rep.total_epochs += e;
+    if (epochs_out) *epochs_out = e;
+    return LR_OK;
+  }
+
+  lr_status solve(double* U_out, double* theta_out, lr_report* out_rep);
+};
+
+lr_status lr_plan_s::solve(double* U_out, double* theta_out, lr_report* out_rep) {
+  rep = lr_report{};
+  epochs.clear();
+  LR_HIP(hipMemsetAsync(dinfo, 0, sizeof(int), st));
+  LR_CHECK(prepare());
+  rep.fro2 = fro2;
+  sched = lr_schedule{};
+  const int64_t cnt = d * p;
+  double theta[LR_MAX_P], resn[LR_MAX_P];
+  if (!replay) {
+    // estimate phase: subspace iteration on A with p columns, then Rayleigh-Ritz
+    LR_HIP(lr::gaussian(Sest, d, p, opt.seed, stream_word(TAG_EST_INIT, 0), st));
+    LR_CHECK(cholqr2(Sest, Sest, p));
+    for (int it = 0; it < opt.est_iters; ++it) {
+      LR_CHECK(applyA(Sest, Y, p));
+      LR_CHECK(cholqr2(Y, Sest, p));
+    }
+    LR_CHECK(applyA(Sest, Y, p));
+    LR_CHECK(gram_dd(Sest, p, Y, p, H));
+    LR_HIP(lr::eigh(H, p, vals, Q, st));
+    LR_HIP(lr::gemm_small(d, p, p, Y, Q, p, Tm1, 0.0, nullptr, st));
+    LR_HIP(lr::gemm_small(d, p, p, Sest, Q, p, Tm2, 0.0, nullptr, st));
+    LR_HIP(lr::residual_norms(Tm1, Tm2, vals, d, p, res, st));
+    LR_CHECK(check_spd());
+    LR_CHECK(read(theta, vals, p * sizeof(double)));
+    LR_CHECK(read(resn, res, p * sizeof(double)));
+    for (int i = 0; i < p; ++i) {
+      rep.theta_est[i] = theta[i];
+      rep.res_est[i] = resn[i];
+    }
+    const double delta = (theta[k - 1] - theta[p - 1]) / 1.5;
+    if (!(delta > 1e-12 * theta[0])) return fail(LR_ENOGAP, "no gap between theta_k and theta_p");
+    double top = 0;
+    for (int i = 0; i < k; ++i) top += theta[i];
+    const double tail = std::max(fro2 - top, 1e-300);
+    const double muF = std::sqrt(fro2 / tail);
+    rep.mu_F = muF;
+    const double eps_stop = eps / (k * muF);
+    const double tau = std::min(1e-2, 0.1 * eps_stop);
+    // Algorithm shiftTune: aim 1/nu_1 ~ lambda - lambda_1 into [Delta/27, Delta/5]
+    const double t1 = theta[0], r1 = resn[0];
+    double lam, mu;
+    if (opt.shift_mode == 1) {
+      lam = 1.5 * t1;
+      mu = std::max(lam - t1 - r1, delta / 30.0);
+    } else {
+      lam = t1 + r1 + delta / 10.0;
+      mu = delta / 10.0;
+    }
+    int rounds = 0;
+    bool ok = false;
+    for (int r = 0; r < opt.max_shift_rounds; ++r) {
+      int64_t b, m;
+      double eta;
+      constants(t1, lam, mu, &b, &eta, &m);
+      LR_CHECK(svrg_solve(Sest, lam, eta, m, b, r, opt.tau_shift, -1, nullptr, nullptr));
+      LR_CHECK(gram_dd(Sest, p, Wt, p, H));
+      LR_HIP(lr::eigh(H, p, vals, Q, st));
+      double nu1;
+      LR_CHECK(read(&nu1, vals, sizeof(double)));
+      if (!(nu1 > 0)) return fail(LR_ESHIFT, "shift estimate not positive");
+      const double g = 1.0 / nu1;
+      if (r < LR_MAX_SHIFT_ROUNDS) {
+        rep.shift_lambda[r] = lam;
+        rep.shift_gap[r] = g;
+      }
+      rounds = r + 1;
+      if (delta / 27.0 <= g && g <= delta / 5.0) {
+        mu = g;
+        ok = true;
+        break;
+      }
+      if (g > delta / 5.0) {
+        lam -= (4.0 / 9.0) * g;
+        mu = (5.0 / 9.0) * g;
+      } else {
+        lam += delta / 10.0;
+        mu = g + delta / 10.0;
+      }
+    }
+    if (!ok) return fail(LR_ESHIFT, "shift tuning did not reach the target interval");
+    rep.shift_rounds = rounds;
+    sched.lambda = lam;
+    sched.mu_hat = mu;
+    sched.delta_hat = delta;
+    constants(t1, lam, mu, &sched.b, &sched.eta, &sched.m);
+    sched.tau = tau;
+    sched.eps_stop = eps_stop;
+    sched.first_solve = rounds;
+  } else {
+    sched = rsched;
+    sched.epochs = nullptr;
+    sched.n_epochs = 0;
+  }
+  // shift-and-invert subspace iteration, p' = p
+  LR_HIP(lr::gaussian(S, d, p, opt.seed, stream_word(TAG_SI_INIT, (uint32_t)sched.first_solve),
+                      st));
+  LR_CHECK(cholqr2(S, S, p));
+  const int L = replay ? rsched.outer : opt.max_outer;
+  bool converged = replay;
+  double change = -1.0;
+  for (int ell = 0; ell < L; ++ell) {
+    int32_t e = 0;
+    LR_CHECK(svrg_solve(S, sched.lambda, sched.eta, sched.m, sched.b, sched.first_solve + ell,
+                        sched.tau, replay ? repochs[ell] : -1, &e, nullptr));
+    epochs.push_back(e);
+    LR_CHECK(gram_dd(S, p, Wt, p, H));
+    LR_HIP(lr::eigh(H, p, vals, Q, st));
+    LR_HIP(lr::gemm_small(d, p, k, S, Q, p, V, 0.0, nullptr, st));
+    LR_CHECK(cholqr2(Wt, S, p));
+    if (ell > 0) {
+      LR_HIP(lr::gram(Vprev, 1, d, k, V, 1, d, k, d, part, kk1, st));
+      LR_HIP(lr::gram(kk1, 1, k, k, kk1, 1, k, k, k, part, kk2, st));
+      LR_HIP(lr::eigh(kk2, k, vals, Q, st));
+      double lmin;
+      LR_CHECK(read(&lmin, vals + (k - 1), sizeof(double)));
+      change = std::sqrt(std::max(0.0, 1.0 - lmin));
+      if (!replay && change <= sched.eps_stop) {
+        converged = true;
+        break;
+      }
+    }
+    std::swap(V, Vprev);
+  }
+  LR_CHECK(check_spd());
+  sched.outer = (int32_t)epochs.size();
+  rep.outer = sched.outer;
+  rep.last_change = change;
+  // final Rayleigh-Ritz with C = XX^T: H = (X^T S)^T (X^T S), one half pass
+  for (int it = 0; it < opt.polish; ++it) {
+    LR_CHECK(applyA(S, Y, p));
+    LR_CHECK(cholqr2(Y, S, p));
+  }
+  LR_HIP(lr::pass_xtw(X, S, p, T, st));
+  LR_HIP(lr::gram(T, p, 1, p, T, p, 1, p, n, part, H, st));
+  LR_HIP(lr::eigh(H, p, vals, Q, st));
+  double* Uo = U_out ? U_out : Tm2;
+  LR_HIP(lr::gemm_small(d, p, k, S, Q, p, Uo, 0.0, nullptr, st));
+  LR_HIP(lr::sign_fix(Uo, d, k, st));
+  double th[LR_MAX_P];
+  LR_CHECK(read(th, vals, k * sizeof(double)));
+  LR_CHECK(check_spd());
+  if (theta_out) std::memcpy(theta_out, th, k * sizeof(double));
+  (void)cnt;
+  if (out_rep) *out_rep = rep;
+  if (!converged) return fail(LR_ENOCONV, "outer iteration reached max_outer");
+  return LR_OK;
+}
+
+extern "C" {
+
+const char* lowrank_status_string(lr_status s) {
+  switch (s) {
+    case LR_OK: return "ok";
+    case LR_EINVAL: return "invalid argument";
+    case LR_ENOMEM: return "out of device memory";
+    case LR_ENOGAP: return "no gap between theta_k and theta_p";
+    case LR_ENOCONV: return "did not converge";
+    case LR_ESHIFT: return "shift not above lambda_1";
+    case LR_ENOTSPD: return "Gram matrix not positive definite";
+    case LR_EDEVICE: return "device error";
+    case LR_EBUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+const char* lowrank_last_error(void) { return g_err.c_str(); }
+
+void lowrank_options_default(lr_options* o) {
+  if (!o) return;
+  *o = lr_options{};
+  o->seed = 0;
+  o->shift_mode = 0;
+  o->est_iters = 4;
+  o->max_outer = 2000;
+  o->max_epochs = 60;
+  o->max_shift_rounds = 30;
+  o->polish = 0;
+  o->batch = 0;
+  o->eta_scale = 1.0;
+  o->tau_shift = 1e-2;
+  o->replay = nullptr;
+  o->timing = 0;
+}
+
+lr_status lowrank_plan(lr_plan* out, const lr_matrix* Xm, int k, int p, double eps,
+                       const lr_options* opt, void* hip_stream) {
+  if (!out) return fail(LR_EINVAL, "null plan pointer");
+  *out = nullptr;
+  if (!Xm || !Xm->values) return fail(LR_EINVAL, "null matrix");
+  if (Xm->layout != LR_DENSE_COLMAJOR) return fail(LR_EINVAL, "only dense column-major X");
+  if (Xm->dtype < LR_F64 || Xm->dtype > LR_BF16) return fail(LR_EINVAL, "bad dtype");
+  const int64_t d = Xm->d, n = Xm->n;
+  if (d < 2 || n < 1 || Xm->ld < d) return fail(LR_EINVAL, "bad sizes");
+  if (!(1 <= k && k < p && p < d) || p > n || p > LR_MAX_P)
+    return fail(LR_EINVAL, "need 1 <= k < p < d, p <= n, p <= 64");
+  if (d > 0x7fffffff || n > 0x7fffffff) return fail(LR_EINVAL, "d and n must fit in int32");
+  if (!(eps > 0)) return fail(LR_EINVAL, "eps must be positive");
+  lr_plan_s* pl = nullptr;
+  try {
+    pl = new lr_plan_s();
+  } catch (...) {
+    return fail(LR_ENOMEM, "host allocation failed");
+  }
+  pl->st = (hipStream_t)hip_stream;
+  pl->X = lr::XView{Xm->values, d, n, Xm->ld, Xm->dtype};
+  pl->k = k;
+  pl->p = p;
+  pl->eps = eps;
+  if (opt)
+    pl->opt = *opt;
+  else
+    lowrank_options_default(&pl->opt);
+  pl->d = d;
+  pl->n = n;
+  int64_t bmax = std::min<int64_t>(n, 8192);
+  bmax = std::max<int64_t>(bmax, std::min<int64_t>(n, pl->opt.batch));
+  if (pl->opt.replay) {
+    const lr_schedule* r = pl->opt.replay;
+    if (r->outer < 0 || (r->outer > 0 && !r->epochs) || r->b < 1 || r->b > n || r->m < 1 ||
+        !(r->lambda > 0) || !(r->eta > 0)) {
+      delete pl;
+      return fail(LR_EINVAL, "bad replay schedule");
+    }
+    pl->replay = true;
+    pl->rsched = *r;
+    pl->repochs.assign(r->epochs, r->epochs + r->outer);
+    pl->rsched.epochs = nullptr;
+    bmax = std::max<int64_t>(bmax, r->b);
+    pl->opt.replay = nullptr;
+  }
+  pl->bmax = bmax;
+  const int64_t dp = d * p;
+  lr_status s = LR_OK;
+  const int nsplit = lr::pass_nsplit(d, n);
+  pl->pb.nsplit = nsplit;
+  const int64_t nbt = (n + 1023) / 1024;
+  const size_t partn = std::max<size_t>((size_t)lr::gram_nblk(std::max(d, n)) * 64 * 64, 1024);
+#define A_(ptr, cnt)                 \
+  if (s == LR_OK) s = pl->alloc(&pl->ptr, (size_t)(cnt));
+  A_(w, n);
+  A_(cdf, n + 1);
+  A_(scratch, 3 * nbt + 8);
+  A_(S, dp);
+  A_(W, dp);
+  A_(Wt, dp);
+  A_(G, dp);
+  A_(Y, dp);
+  A_(Dl, dp);
+  A_(Tm1, dp);
+  A_(Tm2, dp);
+  A_(Sest, dp);
+  A_(V, d * k);
+  A_(Vprev, d * k);
+  A_(T, n * p);
+  A_(Ypart, (int64_t)nsplit * dp);
+  A_(C, bmax * p);
+  A_(scale, bmax);
+  A_(idx, bmax);
+  A_(part, partn);
+  A_(H, 64 * 64);
+  A_(Q, 64 * 64);
+  A_(vals, 64);
+  A_(M, 64 * 64);
+  A_(Rinv, 64 * 64);
+  A_(kk1, 64 * 64);
+  A_(kk2, 64 * 64);
+  A_(res, 64);
+  A_(dfro2, 1);
+  A_(dnorm, 4);
+  A_(dinfo, 1);
+  A_(dbad, 1);
+#undef A_
+  if (s == LR_OK && hipHostMalloc((void**)&pl->hpin, 64 * 64 * sizeof(double) * 2) != hipSuccess) {
+    (void)hipGetLastError();
+    pl->hpin = nullptr;
+    s = fail(LR_ENOMEM, "pinned host allocation failed");
+  }
+  for (int i = 0; s == LR_OK && i < 4; ++i)
+    if (hipEventCreate(&pl->ev[i]) != hipSuccess) s = fail(LR_EDEVICE, "hipEventCreate failed");
+  if (s != LR_OK) {
+    delete pl;
+    return s;
+  }
+  pl->pb.T = pl->T;
+  pl->pb.Ypart = pl->Ypart;
+  *out = pl;
+  return LR_OK;
+}
+
+lr_status lowrank_solve(lr_plan plan, double* U_out, double* theta_out, lr_report* rep) {
+  if (!plan) return fail(LR_EINVAL, "null plan");
+  try {
+    return plan->solve(U_out, theta_out, rep);
+  } catch (...) {
+    return fail(LR_EDEVICE, "unexpected exception");
+  }
+}
+
+lr_status lowrank_get_schedule(lr_plan plan, lr_schedule* out) {
+  if (!plan || !out) return fail(LR_EINVAL, "null argument");
+  int32_t* buf = out->epochs;
+  const int32_t cap = out->n_epochs;
+  *out = plan->sched;
+  out->outer = (int32_t)plan->epochs.size();
+  out->epochs = buf;
+  out->n_epochs = cap;
+  if (buf && cap > 0) {
+    const int32_t c = std::min<int32_t>(cap, out->outer);
+    std::memcpy(buf, plan->epochs.data(), c * sizeof(int32_t));
+  }
+  return LR_OK;
+}
+
+void lowrank_destroy(lr_plan plan) { delete plan; }
+
+lr_status lowrank_op_apply_A(lr_plan plan, const double* W, double* Y, int ncols) {
+  if (!plan || !W || !Y || ncols < 1 || ncols > plan->p) return fail(LR_EINVAL, "bad argument");
+  LR_CHECK(plan->applyA(W, Y, ncols));
+  LR_HIP(hipStreamSynchronize(plan->st));
+  return LR_OK;
+}
+
+lr_status lowrank_op_prepare(lr_plan plan, double* w_out, uint64_t* cdf_out, double* fro2_out) {
+  if (!plan) return fail(LR_EINVAL, "null plan");
+  LR_CHECK(plan->prepare());
+  if (w_out)
+    LR_HIP(hipMemcpyAsync(w_out, plan->w, plan->n * sizeof(double), hipMemcpyDeviceToDevice,
+                          plan->st));
+  if (cdf_out)
+    LR_HIP(hipMemcpyAsync(cdf_out, plan->cdf, (plan->n + 1) * sizeof(uint64_t),
+                          hipMemcpyDeviceToDevice, plan->st));
+  LR_HIP(hipStreamSynchronize(plan->st));
+  if (fro2_out) *fro2_out = plan->fro2;
+  return LR_OK;
+}
+
+lr_status lowrank_op_sample(lr_plan plan, int32_t solve, int32_t epoch, int32_t step, int64_t b,
+                            int32_t* idx_out, double* scale_out) {
+  if (!plan || !idx_out || !scale_out || b < 1 || solve < 0 || epoch < 0 || step < 0 ||
+      solve >= (1 << 28))
+    return fail(LR_EINVAL, "bad argument");
+  if (!plan->prepared) return fail(LR_EINVAL, "call lowrank_op_prepare first");
+  LR_HIP(lr::sample_only(plan->n, plan->cdf, plan->opt.seed, (uint32_t)step, (uint32_t)epoch,
+                         stream_word(TAG_SAMPLES, (uint32_t)solve), b, idx_out, scale_out,
+                         plan->st));
+  LR_HIP(hipStreamSynchronize(plan->st));
+  return LR_OK;
+}
+
+lr_status lowrank_op_gaussian(lr_plan plan, int32_t tag, int32_t solve, int ncols, double* S_out) {
+  if (!plan || !S_out || ncols < 1 || tag < 0 || tag > 15 || solve < 0 || solve >= (1 << 28))
+    return fail(LR_EINVAL, "bad argument");
+  LR_HIP(lr::gaussian(S_out, plan->d, ncols, plan->opt.seed,
+                      stream_word((uint32_t)tag, (uint32_t)solve), plan->st));
+  LR_HIP(hipStreamSynchronize(plan->st));
+  return LR_OK;
+}
+
+lr_status lowrank_op_cholqr2(lr_plan plan, const double* W, double* S_out, int ncols) {
+  if (!plan || !W || !S_out || ncols < 1 || ncols > plan->p) return fail(LR_EINVAL, "bad argument");
+  LR_HIP(hipMemsetAsync(plan->dinfo, 0, sizeof(int), plan->st));
+  LR_CHECK(plan->cholqr2(W, S_out, ncols));
+  LR_CHECK(plan->check_spd());
+  return LR_OK;
+}
+
+lr_status lowrank_op_eigh(lr_plan plan, const double* H, int m, double* vals_out,
+                          double* vecs_out) {
+  if (!plan || !H || !vals_out || !vecs_out || m < 1 || m > LR_MAX_P)
+    return fail(LR_EINVAL, "bad argument");
+  LR_HIP(lr::eigh(H, m, vals_out, vecs_out, plan->st));
+  LR_HIP(hipStreamSynchronize(plan->st));
+  return LR_OK;
+}
+
+lr_status lowrank_op_svrg_solve(lr_plan plan, const double* S, double lambda, double eta,
+                                int64_t m, int64_t b, int32_t solve, int32_t epochs,
+                                double* W_out, double* res_out) {
+  if (!plan || !S || !W_out || m < 1 || b < 1 || b > plan->n || epochs < 0 || solve < 0 ||
+      !(lambda > 0) || !(eta > 0))
+    return fail(LR_EINVAL, "bad argument");
+  if (b > plan->bmax) return fail(LR_EINVAL, "minibatch larger than the plan's workspace");
+  if (!plan->prepared) return fail(LR_EINVAL, "call lowrank_op_prepare first");
+  std::vector<double> hist;
+  int32_t e = 0;
+  LR_CHECK(plan->svrg_solve(S, lambda, eta, m, b, solve, 0.0, epochs, &e, &hist));
+  LR_HIP(hipMemcpyAsync(W_out, plan->Wt, plan->d * plan->p * sizeof(double),
+                        hipMemcpyDeviceToDevice, plan->st));
+  LR_HIP(hipStreamSynchronize(plan->st));
+  if (res_out) std::memcpy(res_out, hist.data(), hist.size() * sizeof(double));
+  return LR_OK;
+}
+
+}  // extern "C"

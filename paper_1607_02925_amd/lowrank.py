@@ -1,0 +1,288 @@
+"""Python binding of liblowrank.so (argument marshalling only).
+
+Tensors are passed by device pointer together with torch's current HIP stream;
+every computation happens in the library's GPU kernels.  There is no CPU or
+PyTorch fallback: if the shared library is missing this module raises on
+import of any entry point.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblowrank.so")
+
+LR_OK, LR_EINVAL, LR_ENOMEM, LR_ENOGAP, LR_ENOCONV, LR_ESHIFT, LR_ENOTSPD, LR_EDEVICE, LR_EBUSY = \
+    range(9)
+LR_MAX_P = 64
+LR_MAX_SHIFT_ROUNDS = 64
+LR_F64, LR_F32, LR_BF16 = 0, 1, 2
+
+
+class lr_matrix(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int64), ("n", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("dtype", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("values", ctypes.c_void_p), ("col_ptr", ctypes.c_void_p),
+                ("row_idx", ctypes.c_void_p)]
+
+
+class lr_schedule(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_double), ("mu_hat", ctypes.c_double),
+                ("delta_hat", ctypes.c_double), ("eta", ctypes.c_double), ("tau", ctypes.c_double),
+                ("eps_stop", ctypes.c_double), ("m", ctypes.c_int64), ("b", ctypes.c_int64),
+                ("first_solve", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("n_epochs", ctypes.c_int32), ("epochs", ctypes.POINTER(ctypes.c_int32))]
+
+
+class lr_options(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("shift_mode", ctypes.c_int32),
+                ("est_iters", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("max_epochs", ctypes.c_int32), ("max_shift_rounds", ctypes.c_int32),
+                ("polish", ctypes.c_int32), ("batch", ctypes.c_int64),
+                ("eta_scale", ctypes.c_double), ("tau_shift", ctypes.c_double),
+                ("replay", ctypes.POINTER(lr_schedule)), ("timing", ctypes.c_int32)]
+
+
+class lr_report(ctypes.Structure):
+    _fields_ = [("theta_est", ctypes.c_double * LR_MAX_P), ("res_est", ctypes.c_double * LR_MAX_P),
+                ("fro2", ctypes.c_double), ("mu_F", ctypes.c_double),
+                ("shift_rounds", ctypes.c_int32),
+                ("shift_lambda", ctypes.c_double * LR_MAX_SHIFT_ROUNDS),
+                ("shift_gap", ctypes.c_double * LR_MAX_SHIFT_ROUNDS),
+                ("outer", ctypes.c_int32), ("total_epochs", ctypes.c_int64),
+                ("passes", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("last_change", ctypes.c_double), ("ms_pass_total", ctypes.c_double),
+                ("ms_steps_total", ctypes.c_double), ("timed_passes", ctypes.c_int64),
+                ("timed_steps", ctypes.c_int64)]
+
+
+# name -> (restype, argtypes); the full exported surface of include/lowrank.h
+_P = ctypes.c_void_p
+SIGNATURES = {
+    "lowrank_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "lowrank_last_error": (ctypes.c_char_p, []),
+    "lowrank_options_default": (None, [ctypes.POINTER(lr_options)]),
+    "lowrank_plan": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(lr_matrix), ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_double, ctypes.POINTER(lr_options), _P]),
+    "lowrank_solve": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(lr_report)]),
+    "lowrank_get_schedule": (ctypes.c_int, [_P, ctypes.POINTER(lr_schedule)]),
+    "lowrank_destroy": (None, [_P]),
+    "lowrank_op_apply_A": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    "lowrank_op_prepare": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "lowrank_op_sample": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int64, _P, _P]),
+    "lowrank_op_gaussian": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _P]),
+    "lowrank_op_cholqr2": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    "lowrank_op_eigh": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P]),
+    "lowrank_op_svrg_solve": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                             ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
+}
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load liblowrank.so and declare every entry point.  Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("liblowrank.so not built: run __graft_entry__.build() "
+                           "(there is no fallback implementation)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class LowRankError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_status_name(code), code, msg))
+        self.code = code
+
+
+def _status_name(code):
+    lib = load_library()
+    return lib.lowrank_status_string(code).decode()
+
+
+def _check(code):
+    if code != LR_OK:
+        lib = load_library()
+        raise LowRankError(code, lib.lowrank_last_error().decode())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t):
+    import torch
+    m = {torch.float64: LR_F64, torch.float32: LR_F32, torch.bfloat16: LR_BF16}
+    if t.dtype not in m:
+        raise ValueError("X must be float64, float32 or bfloat16")
+    return m[t.dtype]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Schedule:
+    """Host copy of lr_schedule; usable as a replay schedule."""
+
+    def __init__(self, lam, mu_hat, eta, m, b, first_solve, outer, epochs, delta_hat=0.0,
+                 tau=0.0, eps_stop=0.0):
+        self.lam, self.mu_hat, self.eta, self.m, self.b = lam, mu_hat, eta, int(m), int(b)
+        self.first_solve, self.outer, self.epochs = int(first_solve), int(outer), list(epochs)
+        self.delta_hat, self.tau, self.eps_stop = delta_hat, tau, eps_stop
+
+    def to_c(self):
+        arr = (ctypes.c_int32 * max(1, len(self.epochs)))(*self.epochs)
+        s = lr_schedule(lam=self.lam, mu_hat=self.mu_hat, delta_hat=self.delta_hat,
+                        eta=self.eta, tau=self.tau, eps_stop=self.eps_stop, m=self.m, b=self.b,
+                        first_solve=self.first_solve, outer=self.outer,
+                        n_epochs=len(self.epochs), epochs=arr)
+        return s, arr
+
+
+class Plan:
+    """A plan over a device matrix X given as an (n, d) C-contiguous tensor, i.e.
+    X (d x n) in column-major order; each row of the tensor is a data point."""
+
+    def __init__(self, Xt, k, p, eps, seed=0, shift_mode=0, est_iters=4, max_outer=2000,
+                 max_epochs=60, max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0,
+                 tau_shift=1e-2, replay=None, timing=0):
+        import torch
+        self.lib = load_library()
+        if not Xt.is_cuda or Xt.dim() != 2 or not Xt.is_contiguous():
+            raise ValueError("X must be a contiguous 2-D device tensor of shape (n, d)")
+        self.Xt = Xt
+        n, d = Xt.shape
+        self.d, self.n, self.k, self.p = d, n, k, p
+        self.device = Xt.device
+        self._mat = lr_matrix(d=d, n=n, ld=d, nnz=0, dtype=_dtype_code(Xt), layout=0,
+                              values=Xt.data_ptr(), col_ptr=None, row_idx=None)
+        opt = lr_options()
+        self.lib.lowrank_options_default(ctypes.byref(opt))
+        opt.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        opt.shift_mode, opt.est_iters, opt.max_outer = shift_mode, est_iters, max_outer
+        opt.max_epochs, opt.max_shift_rounds, opt.polish = max_epochs, max_shift_rounds, polish
+        opt.batch, opt.eta_scale, opt.tau_shift, opt.timing = batch, eta_scale, tau_shift, timing
+        self._replay_keep = None
+        if replay is not None:
+            sc, arr = replay.to_c()
+            self._replay_keep = (sc, arr)
+            opt.replay = ctypes.pointer(sc)
+        self._opt = opt
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.lowrank_plan(ctypes.byref(h), ctypes.byref(self._mat), k, p,
+                                         float(eps), ctypes.byref(opt), _stream()))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.lowrank_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, out=None, raise_on_noconv=False):
+        """Returns (status, U (d x k float64 device tensor), theta (numpy k), report)."""
+        import torch
+        U = out if out is not None else torch.empty((self.k, self.d), dtype=torch.float64,
+                                                     device=self.device)
+        theta = (ctypes.c_double * self.k)()
+        rep = lr_report()
+        with torch.cuda.device(self.device):
+            st = self.lib.lowrank_solve(self._h, _ptr(U), theta, ctypes.byref(rep))
+        if st != LR_OK and (st != LR_ENOCONV or raise_on_noconv):
+            _check(st)
+        # U is d x k column-major == a (k, d) row-major tensor; hand back d x k view
+        return st, U.T, np.array(theta[:]), report_dict(rep, self.p)
+
+    def schedule(self, cap=100000):
+        arr = (ctypes.c_int32 * cap)()
+        s = lr_schedule(epochs=arr, n_epochs=cap)
+        _check(self.lib.lowrank_get_schedule(self._h, ctypes.byref(s)))
+        return Schedule(s.lam, s.mu_hat, s.eta, s.m, s.b, s.first_solve, s.outer,
+                        list(arr[:min(cap, s.outer)]), s.delta_hat, s.tau, s.eps_stop)
+
+    # ---- single steps ----
+    def apply_A(self, W):
+        import torch
+        Wc = W.T.contiguous() if W.shape[0] == self.d else W.contiguous()  # stored (ncols, d)
+        Y = torch.empty_like(Wc)
+        _check(self.lib.lowrank_op_apply_A(self._h, _ptr(Wc), _ptr(Y), Wc.shape[0]))
+        return Y.T
+
+    def prepare(self):
+        import torch
+        w = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        cdf = torch.empty(self.n + 1, dtype=torch.int64, device=self.device)
+        fro2 = ctypes.c_double()
+        _check(self.lib.lowrank_op_prepare(self._h, _ptr(w), _ptr(cdf), ctypes.byref(fro2)))
+        return w, cdf, fro2.value
+
+    def sample(self, solve, epoch, step, b):
+        import torch
+        idx = torch.empty(b, dtype=torch.int32, device=self.device)
+        sc = torch.empty(b, dtype=torch.float64, device=self.device)
+        _check(self.lib.lowrank_op_sample(self._h, solve, epoch, step, b, _ptr(idx), _ptr(sc)))
+        return idx, sc
+
+    def gaussian(self, tag, solve, ncols):
+        import torch
+        S = torch.empty((ncols, self.d), dtype=torch.float64, device=self.device)
+        _check(self.lib.lowrank_op_gaussian(self._h, tag, solve, ncols, _ptr(S)))
+        return S.T
+
+    def cholqr2(self, W):
+        import torch
+        Wc = W.T.contiguous()
+        S = torch.empty_like(Wc)
+        _check(self.lib.lowrank_op_cholqr2(self._h, _ptr(Wc), _ptr(S), Wc.shape[0]))
+        return S.T
+
+    def eigh(self, H):
+        import torch
+        m = H.shape[0]
+        Hc = H.T.contiguous()
+        vals = torch.empty(m, dtype=torch.float64, device=self.device)
+        vecs = torch.empty((m, m), dtype=torch.float64, device=self.device)
+        _check(self.lib.lowrank_op_eigh(self._h, _ptr(Hc), m, _ptr(vals), _ptr(vecs)))
+        return vals, vecs.T
+
+    def svrg_solve(self, S, lam, eta, m, b, solve, epochs):
+        import torch
+        Sc = S.T.contiguous()
+        W = torch.empty_like(Sc)
+        res = (ctypes.c_double * (epochs + 1))()
+        _check(self.lib.lowrank_op_svrg_solve(self._h, _ptr(Sc), float(lam), float(eta), int(m),
+                                              int(b), int(solve), int(epochs), _ptr(W), res))
+        return W.T, np.array(res[:])
+
+
+def report_dict(rep, p):
+    r = rep.shift_rounds
+    return {
+        "theta_est": np.array(rep.theta_est[:p]), "res_est": np.array(rep.res_est[:p]),
+        "fro2": rep.fro2, "mu_F": rep.mu_F, "shift_rounds": r,
+        "shift_lambda": list(rep.shift_lambda[:r]), "shift_gap": list(rep.shift_gap[:r]),
+        "outer": rep.outer, "total_epochs": rep.total_epochs, "passes": rep.passes,
+        "steps": rep.steps, "last_change": rep.last_change,
+        "ms_pass_total": rep.ms_pass_total, "ms_steps_total": rep.ms_steps_total,
+        "timed_passes": rep.timed_passes, "timed_steps": rep.timed_steps,
+    }

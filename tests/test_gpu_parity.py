@@ -1,0 +1,290 @@
+"""Parity of the GPU library (through its C ABI) with the CPU oracle.
+
+Integer and index work (column norms, sampling table, sampled indices) must
+match bit for bit.  Floating-point results are compared with tolerances that
+follow from both sides computing in FP64: single steps to ~1e-12 relative,
+whole trajectories replayed under the oracle's schedule to a principal-angle
+sine of 1e-9, and independent (auto-schedule) runs to 1e-6.
+"""
+import hashlib
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle.linalg import sin_theta
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_02925_amd import lowrank
+    lowrank.load_library()
+    return torch
+
+
+def to_device(torch, xt, storage):
+    if storage == "bf16":
+        return torch.from_numpy(np.ascontiguousarray(xt).view(np.int16)).cuda().view(
+            torch.bfloat16)
+    return torch.from_numpy(np.ascontiguousarray(xt)).cuda()
+
+
+def random_x(d, n, storage, seed, zero_col=None):
+    rng = np.random.default_rng(seed)
+    xt = rng.standard_normal((n, d)) * rng.uniform(0.05, 3.0, size=n)[:, None]
+    if zero_col is not None:
+        xt[zero_col] = 0.0
+    if storage == "f32":
+        xt = xt.astype(np.float32)
+    elif storage == "bf16":
+        xt = workloads.f64_to_bf16_bits(xt)
+    return xt
+
+
+def plan_for(torch, xt, storage, k, p, eps=1e-4, **kw):
+    from paper_1607_02925_amd import lowrank
+    return lowrank.Plan(to_device(torch, xt, storage), k, p, eps, **kw)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_gaussian_block(torch_cuda, storage):
+    xt = random_x(300, 700, storage, 1)
+    plan = plan_for(torch_cuda, xt, storage, 2, 5, seed=0xABCDEF0123)
+    for tag, solve, p in [(1, 0, 5), (2, 3, 5), (2, 7, 3)]:
+        g = plan.gaussian(tag, solve, p).cpu().numpy()
+        o = oracle.gaussian_block(0xABCDEF0123, tag, solve, 300, p)
+        np.testing.assert_allclose(g, o, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_sampling_table_and_indices_bit_exact(torch_cuda, storage):
+    d, n = 301, 5003
+    xt = random_x(d, n, storage, 2, zero_col=17)
+    plan = plan_for(torch_cuda, xt, storage, 2, 6, seed=0x1607)
+    w, cdf, fro2 = plan.prepare()
+    X = oracle.decode(xt, storage)
+    w_o = oracle.column_sq_norms(X)
+    assert np.array_equal(w.cpu().numpy(), w_o)
+    _, qc = oracle.build_table(w_o)
+    assert np.array_equal(cdf.cpu().numpy().view(np.uint64), qc)
+    assert abs(fro2 - w_o.sum()) <= 1e-12 * w_o.sum()
+    for solve, epoch, step, b in [(0, 0, 0, 256), (5, 2, 17, 1000), (40, 11, 123, 4097)]:
+        idx, sc = plan.sample(solve, epoch, step, b)
+        i_o, s_o = oracle.step_indices(0x1607, solve, epoch, step, b, qc)
+        assert np.array_equal(idx.cpu().numpy().astype(np.int64), i_o)
+        assert np.array_equal(sc.cpu().numpy(), s_o)
+        assert 17 not in set(idx.cpu().numpy().tolist())
+
+
+@pytest.mark.parametrize("storage,d,n,p", [("f64", 256, 2048, 8), ("f32", 333, 4097, 20),
+                                           ("bf16", 520, 3001, 48), ("f32", 130, 999, 64),
+                                           ("f64", 77, 300, 5)])
+def test_apply_A(torch_cuda, storage, d, n, p):
+    torch = torch_cuda
+    xt = random_x(d, n, storage, 3)
+    plan = plan_for(torch, xt, storage, 1, min(p, d - 1))
+    W = np.random.default_rng(4).standard_normal((d, min(p, d - 1)))
+    Y = plan.apply_A(torch.from_numpy(W).cuda()).cpu().numpy()
+    X = oracle.decode(xt, storage)
+    ref = oracle.apply_A(X, W)
+    assert np.linalg.norm(Y - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_cholqr2_and_eigh(torch_cuda):
+    torch = torch_cuda
+    xt = random_x(200, 400, "f64", 5)
+    plan = plan_for(torch, xt, "f64", 4, 40)
+    rng = np.random.default_rng(6)
+    for p in (3, 17, 40):
+        W = rng.standard_normal((200, p)) @ np.diag(np.logspace(0, 3, p))
+        S = plan.cholqr2(torch.from_numpy(W).cuda()).cpu().numpy()
+        So, _ = oracle.cholqr2(W)
+        assert np.linalg.norm(S - So) < 1e-12 * math.sqrt(p)
+    for m in (1, 2, 7, 40, 64):
+        B = rng.standard_normal((m, m))
+        H = B + B.T + np.diag(np.arange(m) * 3.0)
+        vals, vecs = plan.eigh(torch.from_numpy(H).cuda())
+        vo, Qo = oracle.eigh_desc(H)
+        np.testing.assert_allclose(vals.cpu().numpy(), vo, rtol=0, atol=1e-12 * np.abs(vo).max())
+        assert np.linalg.norm(vecs.cpu().numpy() - Qo) < 1e-10
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_svrg_solve_fixed_epochs(torch_cuda, storage):
+    torch = torch_cuda
+    d, n, p = 70, 1500, 6
+    sig = np.concatenate([[3.0, 2.6, 2.3], np.linspace(1.2, 0.05, d - 3)])
+    rng = np.random.default_rng(7)
+    U = np.linalg.qr(rng.standard_normal((d, d)))[0]
+    V = np.linalg.qr(rng.standard_normal((n, d)))[0]
+    xt = (V * sig) @ U.T
+    if storage == "f32":
+        xt = xt.astype(np.float32)
+    elif storage == "bf16":
+        xt = workloads.f64_to_bf16_bits(xt)
+    X = oracle.decode(xt, storage)
+    plan = plan_for(torch, xt, storage, 2, p, seed=99)
+    plan.prepare()
+    w = oracle.column_sq_norms(X)
+    _, qc = oracle.build_table(w)
+    S = oracle.cholqr2(rng.standard_normal((d, p)))[0]
+    lam1 = np.linalg.norm(X, 2) ** 2
+    lam = lam1 + 0.3
+    b, eta, m = oracle.solver_constants(w.sum(), lam1, lam, 0.3, n)
+    Wg, res_g = plan.svrg_solve(torch.from_numpy(S).cuda(), lam, eta, m, b, 4, 3)
+    Wo, e, res_o = oracle.svrg_solve(X, qc, S, lam, eta, m, b, 0.0, 99, 4, 60, fixed_epochs=3)
+    Wg = Wg.cpu().numpy()
+    assert np.linalg.norm(Wg - Wo) <= 1e-10 * np.linalg.norm(Wo)
+    np.testing.assert_allclose(res_g, res_o, rtol=1e-7)
+    assert res_o[-1] < 0.2 * res_o[0]
+
+
+def _schedule_from_oracle(r):
+    from paper_1607_02925_amd import lowrank
+    s = r.schedule
+    return lowrank.Schedule(s.lam, s.mu_hat, s.eta, s.m, s.b, s.first_solve, s.outer, s.epochs)
+
+
+@pytest.fixture(scope="module")
+def cfg1(torch_cuda):
+    w = workloads.workload("planted-256x2048-f64")
+    ref = oracle.solve(w["Xt"], w["storage"], w["k"], w["p"], w["eps"],
+                       oracle.Options(seed=w["solver_seed"]))
+    return w, ref
+
+
+def test_solve_auto_matches_oracle_decisions(torch_cuda, cfg1):
+    w, ref = cfg1
+    plan = plan_for(torch_cuda, w["Xt"], w["storage"], w["k"], w["p"], w["eps"],
+                    seed=w["solver_seed"])
+    st, U, theta, rep = plan.solve()
+    assert st == 0
+    sc = plan.schedule()
+    rs = ref.schedule
+    assert rep["shift_rounds"] == ref.shift_rounds == sc.first_solve
+    assert (sc.b, sc.m, sc.outer) == (rs.b, rs.m, rs.outer)
+    assert sc.epochs == rs.epochs
+    # lambda = theta_1 + ||r_1|| + Delta/10; on this input ||r_1|| is itself at the
+    # rounding level of a difference of two O(theta_1) vectors, so lambda and eta
+    # agree to that level (every discrete decision above must match exactly)
+    assert abs(sc.lam - rs.lam) <= 1e-10 * rs.lam
+    assert abs(sc.eta - rs.eta) <= 1e-10 * rs.eta
+    np.testing.assert_allclose(rep["theta_est"], ref.theta_est, rtol=1e-11)
+    Ug = U.cpu().numpy()
+    assert np.linalg.norm(Ug.T @ Ug - np.eye(w["k"])) < 1e-13
+    assert sin_theta(ref.U, Ug) <= 1e-6
+    np.testing.assert_allclose(theta, ref.theta, rtol=1e-10)
+    # the planted answer: noise-free X = U Sigma V^T
+    assert sin_theta(w["U"][:, :w["k"]], Ug) < 1e-8
+
+
+def test_solve_replay_trajectory(torch_cuda, cfg1):
+    w, ref = cfg1
+    plan = plan_for(torch_cuda, w["Xt"], w["storage"], w["k"], w["p"], w["eps"],
+                    seed=w["solver_seed"], replay=_schedule_from_oracle(ref))
+    st, U, theta, rep = plan.solve()
+    assert st == 0 and rep["outer"] == ref.schedule.outer
+    assert sin_theta(ref.U, U.cpu().numpy()) <= 1e-9
+    np.testing.assert_allclose(theta, ref.theta, rtol=1e-12)
+
+
+def _fixture_or_oracle(name, max_outer):
+    import sys
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    import make_oracle_fixtures as mk
+    w = workloads.workload(name)
+    path = mk.fixture_path(name, max_outer)
+    h = hashlib.sha256(np.ascontiguousarray(w["Xt"]).tobytes()).hexdigest()
+    if os.path.exists(path):
+        z = np.load(path)
+        if str(z["input_sha256"]) == h:
+            from paper_1607_02925_amd import lowrank
+            sched = lowrank.Schedule(float(z["lam"]), float(z["mu_hat"]), float(z["eta"]),
+                                     int(z["m"]), int(z["b"]), int(z["first_solve"]),
+                                     int(z["outer"]), [int(e) for e in z["epochs"]])
+            return w, z["U"], z["theta"], sched, float(z["eps_stop"])
+        print("fixture input hash differs; running the oracle", flush=True)
+    opt = oracle.Options(seed=w["solver_seed"])
+    if max_outer is not None:
+        opt.max_outer = max_outer
+    r = oracle.solve(w["Xt"], w["storage"], w["k"], w["p"], w["eps"], opt)
+    return w, r.U, r.theta, _schedule_from_oracle(r), r.schedule.eps_stop
+
+
+def test_geometric_f32_replay_and_auto(torch_cuda):
+    w, Uo, tho, sched, eps_stop = _fixture_or_oracle("planted-256x8192-f32", None)
+    plan = plan_for(torch_cuda, w["Xt"], w["storage"], w["k"], w["p"], w["eps"],
+                    seed=w["solver_seed"], replay=sched)
+    st, U, theta, _ = plan.solve()
+    assert st == 0
+    assert sin_theta(Uo, U.cpu().numpy()) <= 1e-9
+    np.testing.assert_allclose(theta, tho, rtol=1e-11)
+    plan = plan_for(torch_cuda, w["Xt"], w["storage"], w["k"], w["p"], w["eps"],
+                    seed=w["solver_seed"])
+    st, U, theta, rep = plan.solve()
+    assert st == 0
+    sc = plan.schedule()
+    assert (sc.first_solve, sc.b, sc.m) == (sched.first_solve, sched.b, sched.m)
+    assert sin_theta(Uo, U.cpu().numpy()) <= 1e-6
+    np.testing.assert_allclose(theta, tho, rtol=1e-9)
+
+
+def test_powerlaw_bf16_prefix_trajectory(torch_cuda):
+    w, Uo, tho, sched, _ = _fixture_or_oracle("planted-512x16384-bf16", 3)
+    plan = plan_for(torch_cuda, w["Xt"], w["storage"], w["k"], w["p"], w["eps"],
+                    seed=w["solver_seed"], replay=sched)
+    st, U, theta, _ = plan.solve()
+    assert st == 0
+    assert sin_theta(Uo, U.cpu().numpy()) <= 1e-9
+    np.testing.assert_allclose(theta, tho, rtol=1e-11)
+
+
+@pytest.mark.parametrize("d,n,k,p,storage", [(97, 613, 1, 3, "f32"), (130, 257, 3, 9, "bf16"),
+                                             (64, 65, 2, 5, "f64")])
+def test_ragged_shapes_auto(torch_cuda, d, n, k, p, storage):
+    i = np.arange(1, d + 1, dtype=float)
+    sig = np.where(i <= k, 2.0 - 0.1 * i, 0.8 * i ** -0.5)
+    data = workloads.planted_dense(d, n, sig[:min(d, n)], 31 + d, storage)
+    xt = data["Xt"]
+    ref = oracle.solve(xt, storage, k, p, 1e-6, oracle.Options(seed=5))
+    plan = plan_for(torch_cuda, xt, storage, k, p, 1e-6, seed=5)
+    st, U, theta, _ = plan.solve()
+    assert st == ref.status == 0
+    sc = plan.schedule()
+    assert sc.epochs == ref.schedule.epochs
+    assert sin_theta(ref.U, U.cpu().numpy()) <= 1e-6
+    np.testing.assert_allclose(theta, ref.theta, rtol=1e-9)
+
+
+def test_error_statuses(torch_cuda):
+    from paper_1607_02925_amd import lowrank
+    xt = random_x(40, 300, "f32", 9)
+    xt[11, 7] = np.nan
+    plan = plan_for(torch_cuda, xt, "f32", 2, 4)
+    with pytest.raises(lowrank.LowRankError) as ei:
+        plan.solve()
+    assert ei.value.code == lowrank.LR_EINVAL
+    sig = np.ones(20)
+    sig[0] = 2.0
+    data = workloads.planted_dense(20, 100, sig, 3, "f64")
+    plan = plan_for(torch_cuda, data["Xt"], "f64", 2, 4)
+    with pytest.raises(lowrank.LowRankError) as ei:
+        plan.solve()
+    assert ei.value.code == lowrank.LR_ENOGAP
+    # a replayed shift below lambda_1 makes the inner solver diverge
+    data = workloads.planted_dense(30, 200, np.linspace(2.0, 0.1, 30), 4, "f64")
+    bad = lowrank.Schedule(0.5 * 4.0, 0.1, 0.1, 50, 64, 0, 2, [5, 5])
+    plan = plan_for(torch_cuda, data["Xt"], "f64", 2, 4, replay=bad)
+    with pytest.raises(lowrank.LowRankError) as ei:
+        plan.solve()
+    assert ei.value.code == lowrank.LR_ESHIFT
