@@ -1,0 +1,220 @@
+"""Benchmark of the shift-and-invert low-rank path on one MI355X.
+
+A step is one whole lowrank_solve (sampling table, estimate phase, shift
+tuning, shift-and-invert subspace iteration with SVRG inner solves, final
+Rayleigh-Ritz) on one resident synthetic matrix: the planted-spectrum
+2048 x 200000 FP32 workload (sigma_1..10 geometric 10 -> 5, sigma_11 = 4.95,
+sigma_i = 4 (i - 10)^-0.8 beyond, N(0, 1e-4^2) noise; k = 10, p = 20,
+eps = 1e-4).  Prints one JSON line.
+
+Modes for profiler runs: --mode solve (default), --mode pass (only the
+X (X^T W) pass, --steps times), --mode copy (a device copy of the same bytes as
+X, used to calibrate HBM byte counters).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+WORKLOAD = "planted-2048x200000-f32"
+METRIC = "solves/s + HBM GB/s at ε=1e-4 (plain FP32 vs BF16 batched); p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", default="solve", choices=["solve", "pass", "copy"])
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    pos = (len(xs) - 1) * q
+    lo, hi = int(math.floor(pos)), int(math.ceil(pos))
+    return xs[lo] + (xs[hi] - xs[lo]) * (pos - lo)
+
+
+def cpu_baseline(Xt_dev, w, sched, rep):
+    """Time the oracle (NumPy FP64) on a bounded sample of the same workload:
+    the sampling table, one X(X^T S) pass and one inner-solver epoch at full
+    size, then scale to a whole solve with the pass and epoch counts of the
+    GPU run."""
+    import numpy as np
+    import oracle
+    from threadpoolctl import threadpool_info
+    t0 = time.time()
+    xt = Xt_dev.cpu().numpy()
+    X = oracle.decode(xt, w["storage"])
+    t_prep0 = time.time()
+    wn = oracle.column_sq_norms(X)
+    _, qc = oracle.build_table(wn)
+    t_prep = time.time() - t_prep0
+    d, p = X.shape[0], w["p"]
+    S = oracle.cholqr2(oracle.gaussian_block(w["solver_seed"], 2, 0, d, p))[0]
+    t1 = time.time()
+    oracle.apply_A(X, S)
+    t_pass = time.time() - t1
+    t2 = time.time()
+    oracle.svrg_solve(X, qc, S, sched.lam, sched.eta, sched.m, sched.b, 0.0, w["solver_seed"],
+                      sched.first_solve, 60, fixed_epochs=1)
+    t_epoch_incl = time.time() - t2   # warm-start pass + one epoch (steps + residual pass)
+    t_steps = max(t_epoch_incl - 2 * t_pass, 0.0)
+    est = t_prep + rep["passes"] * t_pass + rep["total_epochs"] * t_steps
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    log("cpu baseline: prep %.2fs pass %.2fs epoch-steps %.2fs -> est %.1fs per solve "
+        "(sample wall %.1fs)" % (t_prep, t_pass, t_steps, est, time.time() - t0))
+    return {"value": 1.0 / est, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": "oracle (NumPy FP64) on the full-size workload: sampling table, one "
+                      "X(X^T S) pass and one inner-solver epoch (m=%d steps, b=%d) timed, "
+                      "scaled by the GPU run's %d passes and %d epochs per solve"
+                      % (sched.m, sched.b, rep["passes"], rep["total_epochs"])}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1607_02925_amd import lowrank
+
+    lowrank.load_library()
+    dev = "cuda:0"
+    w = dict(workloads.WORKLOADS[args.workload])
+    t0 = time.time()
+    data = workloads.workload(args.workload, device=dev)
+    Xt = data["Xt"]
+    torch.cuda.synchronize()
+    log("generated %s on the GPU in %.1fs" % (args.workload, time.time() - t0))
+    x_bytes = Xt.numel() * Xt.element_size()
+    d, n, k, p = w["d"], w["n"], w["k"], w["p"]
+
+    if args.mode == "copy":
+        dst = torch.empty_like(Xt)
+        for _ in range(args.warmup):
+            dst.copy_(Xt)
+        torch.cuda.synchronize()
+        t = time.time()
+        for _ in range(args.steps):
+            dst.copy_(Xt)
+        torch.cuda.synchronize()
+        dt = (time.time() - t) / args.steps
+        print(json.dumps({"mode": "copy", "bytes_read": x_bytes, "bytes_written": x_bytes,
+                          "ms": dt * 1e3, "GBps": 2 * x_bytes / dt / 1e9}), flush=True)
+        return
+
+    plan = lowrank.Plan(Xt, k, p, w["eps"], seed=w["solver_seed"], timing=1)
+
+    if args.mode == "pass":
+        Wm = torch.randn((p, d), dtype=torch.float64, device=dev).T
+        for _ in range(args.warmup):
+            plan.apply_A(Wm)
+        torch.cuda.synchronize()
+        t = time.time()
+        for _ in range(args.steps):
+            plan.apply_A(Wm)
+        torch.cuda.synchronize()
+        dt = (time.time() - t) / args.steps
+        print(json.dumps({"mode": "pass", "ms": dt * 1e3, "x_bytes": x_bytes,
+                          "GBps_alg": x_bytes / dt / 1e9}), flush=True)
+        return
+
+    for i in range(args.warmup):
+        st, U, theta, rep = plan.solve()
+        log("warmup %d: status %d outer %d epochs %d" % (i, st, rep["outer"],
+                                                         rep["total_epochs"]))
+    torch.cuda.synchronize()
+    lat = []
+    reps = []
+    t_start = time.time()
+    for i in range(args.steps):
+        ts = time.time()
+        st, U, theta, rep = plan.solve()
+        torch.cuda.synchronize()
+        lat.append(time.time() - ts)
+        reps.append(rep)
+        log("step %d: %.3fs status %d outer %d epochs %d passes %d steps %d" %
+            (i, lat[-1], st, rep["outer"], rep["total_epochs"], rep["passes"], rep["steps"]))
+    torch.cuda.synchronize()
+    total = time.time() - t_start
+    sched = plan.schedule()
+    rep = reps[-1]
+
+    # dominant kernel: the per-step update (gathers b columns, updates the d x p difference)
+    sx = Xt.element_size()
+    b = sched.b
+    bytes_update = b * d * sx + b * p * 8 + 3 * d * p * 8
+    bytes_sdot = b * d * sx + d * p * 8 + b * p * (8 + 8) + b * 4
+    probes = sum(r["probes"] for r in reps)
+    ms_upd = sum(r["ms_update_probe"] for r in reps) / max(probes, 1)
+    ms_sdot = sum(r["ms_sample_dot_probe"] for r in reps) / max(probes, 1)
+    ms_pass = sum(r["ms_pass_total"] for r in reps) / max(sum(r["timed_passes"] for r in reps), 1)
+    t_upd_total = ms_upd * rep["steps"]
+    t_sdot_total = ms_sdot * rep["steps"]
+    t_pass_total = ms_pass * rep["passes"]
+    kernels = {
+        "k_update": (t_upd_total, bytes_update, ms_upd),
+        "k_sample_dot": (t_sdot_total, bytes_sdot, ms_sdot),
+    }
+    dom = max(kernels, key=lambda kk: kernels[kk][0])
+    _, dbytes, dms = kernels[dom]
+    achieved = dbytes / (dms * 1e-3) / 1e9 if dms > 0 else None
+    pass_gbs = x_bytes / (ms_pass * 1e-3) / 1e9 if ms_pass > 0 else None
+    pass_tflops = 4.0 * d * n * p / (ms_pass * 1e-3) / 1e12 if ms_pass > 0 else None
+    out = {
+        "metric": METRIC,
+        "value": args.steps / total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic planted-spectrum matrix generated on the GPU from fixed seeds",
+        "config": {"workload": args.workload, "d": d, "n": n, "k": k, "p": p, "eps": w["eps"],
+                   "storage": w["storage"], "form": "per-request",
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": percentile(lat, 0.5) * 1e3, "p99": percentile(lat, 0.99) * 1e3},
+        "pass": {"ms": ms_pass, "hbm_GBps_alg": pass_gbs, "fp64_TFLOPs": pass_tflops,
+                 "frac_hbm": pass_gbs / PEAK_HBM_GBS if pass_gbs else None},
+        "solve": {"status": st, "outer": rep["outer"], "epochs": rep["total_epochs"],
+                  "passes": rep["passes"], "inner_steps": rep["steps"],
+                  "shift_rounds": rep["shift_rounds"], "lambda": sched.lam, "m": sched.m,
+                  "b": sched.b, "share_update": t_upd_total / (total / args.steps * 1e3),
+                  "share_sample_dot": t_sdot_total / (total / args.steps * 1e3),
+                  "share_pass": t_pass_total / (total / args.steps * 1e3)},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS if achieved else None,
+                     "traffic": None, "bytes_per_launch": dbytes, "avg_launch_ms": dms},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(Xt, dict(w, **data), sched, rep)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -54,6 +54,8 @@ struct lr_plan_s {
   lr_schedule rsched{};
   std::vector<int32_t> repochs;
   int64_t d = 0, n = 0, bmax = 0;
+  int PC = 0;                     // padded row stride of T and C
+  static constexpr int64_t MCH = 256;  // inner steps whose draws are made in one launch
 
   std::vector<void*> allocs;
   double *w = nullptr, *S = nullptr, *W = nullptr, *Wt = nullptr, *G = nullptr, *Y = nullptr;
@@ -67,7 +69,7 @@ struct lr_plan_s {
   int *dinfo = nullptr, *dbad = nullptr;
   double* hpin = nullptr;
   lr::PassBufs pb{};
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[7] = {};
 
   bool prepared = false;
   double fro2 = 0;
@@ -113,8 +115,8 @@ struct lr_plan_s {
   lr_status applyA(const double* Win, double* Yout, int ncols, double alpha = 1.0,
                    const double* A = nullptr, double beta = 0.0, const double* B = nullptr,
                    double gamma = 0.0) {
-    LR_HIP(lr::pass_xtw(X, Win, ncols, T, st));
-    LR_HIP(lr::pass_xt(X, T, ncols, pb, alpha, A, beta, B, gamma, Yout, st));
+    LR_HIP(lr::pass_xtw(X, Win, ncols, T, PC, st));
+    LR_HIP(lr::pass_xt(X, T, PC, ncols, pb, alpha, A, beta, B, gamma, Yout, st));
     rep.passes++;
     return LR_OK;
   }
@@ -198,10 +200,20 @@ struct lr_plan_s {
       }
       LR_HIP(hipMemsetAsync(Dl, 0, cnt * sizeof(double), st));
       if (opt.timing) LR_HIP(hipEventRecord(ev[0], st));
-      for (int64_t t = 0; t < m; ++t) {
-        LR_HIP(lr::step_sample_dot(X, p, cdf, opt.seed, (uint32_t)t, (uint32_t)e, w3, b, Dl, idx,
-                                   scale, C, st));
-        LR_HIP(lr::step_update(X, p, b, idx, C, G, Dl, lam, eta, st));
+      const int64_t tprobe = m / 2;  // one launch per epoch is timed per kernel
+      for (int64_t t0 = 0; t0 < m; t0 += MCH) {
+        const int64_t nst = std::min(MCH, m - t0);
+        LR_HIP(lr::draw_chunk(n, cdf, opt.seed, (uint32_t)t0, nst, (uint32_t)e, w3, b, idx, scale,
+                              st));
+        for (int64_t t = t0; t < t0 + nst; ++t) {
+          const bool probe = opt.timing && t == tprobe;
+          const int32_t* it = idx + (t - t0) * b;
+          if (probe) LR_HIP(hipEventRecord(ev[4], st));
+          LR_HIP(lr::step_dot(X, p, b, it, scale + (t - t0) * b, Dl, C, PC, st));
+          if (probe) LR_HIP(hipEventRecord(ev[5], st));
+          LR_HIP(lr::step_update(X, p, b, it, C, PC, G, Dl, lam, eta, st));
+          if (probe) LR_HIP(hipEventRecord(ev[6], st));
+        }
       }
       if (opt.timing) LR_HIP(hipEventRecord(ev[1], st));
       rep.steps += m;
@@ -220,6 +232,11 @@ struct lr_plan_s {
         LR_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
         rep.ms_pass_total += ms;
         rep.timed_passes += 1;
+        LR_HIP(hipEventElapsedTime(&ms, ev[4], ev[5]));
+        rep.ms_sample_dot_probe += ms;
+        LR_HIP(hipEventElapsedTime(&ms, ev[5], ev[6]));
+        rep.ms_update_probe += ms;
+        rep.probes += 1;
       }
       ++e;
       if (hist) hist->push_back(r);
@@ -367,8 +384,8 @@ lr_status lr_plan_s::solve(double* U_out, double* theta_out, lr_report* out_rep)
     LR_CHECK(applyA(S, Y, p));
     LR_CHECK(cholqr2(Y, S, p));
   }
-  LR_HIP(lr::pass_xtw(X, S, p, T, st));
-  LR_HIP(lr::gram(T, p, 1, p, T, p, 1, p, n, part, H, st));
+  LR_HIP(lr::pass_xtw(X, S, p, T, PC, st));
+  LR_HIP(lr::gram(T, PC, 1, p, T, PC, 1, p, n, part, H, st));
   LR_HIP(lr::eigh(H, p, vals, Q, st));
   double* Uo = U_out ? U_out : Tm2;
   LR_HIP(lr::gemm_small(d, p, k, S, Q, p, Uo, 0.0, nullptr, st));
@@ -449,11 +466,15 @@ lr_status lowrank_plan(lr_plan* out, const lr_matrix* Xm, int k, int p, double e
     lowrank_options_default(&pl->opt);
   pl->d = d;
   pl->n = n;
+  if (pl->opt.batch < 0 || pl->opt.batch > 8192) {
+    delete pl;
+    return fail(LR_EINVAL, "batch must be in [0, 8192]");
+  }
   int64_t bmax = std::min<int64_t>(n, 8192);
-  bmax = std::max<int64_t>(bmax, std::min<int64_t>(n, pl->opt.batch));
   if (pl->opt.replay) {
     const lr_schedule* r = pl->opt.replay;
-    if (r->outer < 0 || (r->outer > 0 && !r->epochs) || r->b < 1 || r->b > n || r->m < 1 ||
+    if (r->outer < 0 || (r->outer > 0 && !r->epochs) || r->b < 1 || r->b > n || r->b > 8192 ||
+        r->m < 1 ||
         !(r->lambda > 0) || !(r->eta > 0)) {
       delete pl;
       return fail(LR_EINVAL, "bad replay schedule");
@@ -462,14 +483,12 @@ lr_status lowrank_plan(lr_plan* out, const lr_matrix* Xm, int k, int p, double e
     pl->rsched = *r;
     pl->repochs.assign(r->epochs, r->epochs + r->outer);
     pl->rsched.epochs = nullptr;
-    bmax = std::max<int64_t>(bmax, r->b);
     pl->opt.replay = nullptr;
   }
   pl->bmax = bmax;
+  pl->PC = lr::pad16(p);
   const int64_t dp = d * p;
   lr_status s = LR_OK;
-  const int nsplit = lr::pass_nsplit(d, n);
-  pl->pb.nsplit = nsplit;
   const int64_t nbt = (n + 1023) / 1024;
   const size_t partn = std::max<size_t>((size_t)lr::gram_nblk(std::max(d, n)) * 64 * 64, 1024);
 #define A_(ptr, cnt)                 \
@@ -488,11 +507,13 @@ lr_status lowrank_plan(lr_plan* out, const lr_matrix* Xm, int k, int p, double e
   A_(Sest, dp);
   A_(V, d * k);
   A_(Vprev, d * k);
-  A_(T, n * p);
+  A_(T, n * lr::pad16(p));
+  const int nsplit = lr::pass_nsplit(d, n);
+  pl->pb.nsplit = nsplit;
   A_(Ypart, (int64_t)nsplit * dp);
-  A_(C, bmax * p);
-  A_(scale, bmax);
-  A_(idx, bmax);
+  A_(C, bmax * lr::pad16(p));
+  A_(scale, lr_plan_s::MCH * bmax);
+  A_(idx, lr_plan_s::MCH * bmax);
   A_(part, partn);
   A_(H, 64 * 64);
   A_(Q, 64 * 64);
@@ -512,13 +533,12 @@ lr_status lowrank_plan(lr_plan* out, const lr_matrix* Xm, int k, int p, double e
     pl->hpin = nullptr;
     s = fail(LR_ENOMEM, "pinned host allocation failed");
   }
-  for (int i = 0; s == LR_OK && i < 4; ++i)
+  for (int i = 0; s == LR_OK && i < 7; ++i)
     if (hipEventCreate(&pl->ev[i]) != hipSuccess) s = fail(LR_EDEVICE, "hipEventCreate failed");
   if (s != LR_OK) {
     delete pl;
     return s;
   }
-  pl->pb.T = pl->T;
   pl->pb.Ypart = pl->Ypart;
   *out = pl;
   return LR_OK;

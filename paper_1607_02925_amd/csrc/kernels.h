@@ -24,28 +24,31 @@ hipError_t build_table(const double* w, int64_t n, uint64_t* cdf, double* fro2, 
 // S (d x p) Gaussian block from Philox stream (tag, solve).
 hipError_t gaussian(double* S, int64_t d, int p, uint64_t seed, uint32_t word3, hipStream_t st);
 
-// T = X^T W (n x p, row-major) ; Y = X T reduced with epilogue
-// out = alpha * (X T) + beta * A + gamma * B  (A, B may be null).
+// Pass: T = X^T W (n x PC row-major, PC = pad16(p), padded columns zero), then
+// out = alpha * X T + beta * A + gamma * B  (A, B may be null; d x p).
 struct PassBufs {
-  double* T;       // n * p
-  double* Ypart;   // nsplit * d * p
+  double* Ypart;   // nsplit * d * p partial sums
   int nsplit;
 };
+int pad16(int p);
 int pass_nsplit(int64_t d, int64_t n);
-hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, hipStream_t st);
-hipError_t pass_xt(const XView& X, const double* T, int p, const PassBufs& pb, double alpha,
-                   const double* A, double beta, const double* B, double gamma, double* out,
-                   hipStream_t st);
+hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, hipStream_t st);
+hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBufs& pb,
+                   double alpha, const double* A, double beta, const double* B, double gamma,
+                   double* out, hipStream_t st);
 
-// Inner step, part 1: draw b indices (Philox + inverse CDF) and
-// C = diag(1/(b pi)) X_B^T Dl   (C: b x p row-major).
-hipError_t step_sample_dot(const XView& X, int p, const uint64_t* cdf, uint64_t seed,
-                           uint32_t step, uint32_t epoch, uint32_t word3, int64_t b,
-                           const double* Dl, int32_t* idx, double* scale, double* C,
-                           hipStream_t st);
-// Inner step, part 2: Dl <- Dl - eta (G + lam Dl - X_B C).
+// Column draws of `steps` inner steps starting at step t0 of one epoch:
+// idx/scale[(t - t0) * b + j].
+hipError_t draw_chunk(int64_t n, const uint64_t* cdf, uint64_t seed, uint32_t t0, int64_t steps,
+                      uint32_t epoch, uint32_t word3, int64_t b, int32_t* idx, double* scale,
+                      hipStream_t st);
+// Inner step, part 1: C = diag(scale) X_B^T Dl   (C: b x PC row-major).
+hipError_t step_dot(const XView& X, int p, int64_t b, const int32_t* idx, const double* scale,
+                    const double* Dl, double* C, int PC, hipStream_t st);
+// Inner step, part 2: Dl <- Dl - eta (G + lam Dl - X_B C).  b <= 8192.
 hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, const double* C,
-                       const double* G, double* Dl, double lam, double eta, hipStream_t st);
+                       int PC, const double* G, double* Dl, double lam, double eta,
+                       hipStream_t st);
 // Draw only (for testing the sampler).
 hipError_t sample_only(int64_t n, const uint64_t* cdf, uint64_t seed, uint32_t step,
                        uint32_t epoch, uint32_t word3, int64_t b, int32_t* idx, double* scale,

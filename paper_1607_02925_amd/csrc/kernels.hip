@@ -5,6 +5,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace lr {
 namespace {
 
@@ -253,78 +255,203 @@ __global__ __launch_bounds__(NT) void k_gauss(double* __restrict__ S, int64_t d,
 }
 
 // ---------------------------------------------------------------------------
-// Pass, first half: T = X^T W.  One thread per column of X; a workgroup
-// stages a 16-row x 256-column slab of X in LDS with coalesced loads, and
-// every thread reads the wave-uniform W values as scalars.
-constexpr int XTW_RC = 16;
-template <typename TX, int PM>
-__global__ __launch_bounds__(NT) void k_xtw(const TX* __restrict__ X, int64_t ld, int64_t d,
-                                            int64_t n, int p, const double* __restrict__ W,
-                                            double* __restrict__ T) {
-  __shared__ double xs[XTW_RC][NT + 1];
-  const int t = threadIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.x * NT;
-  double acc[PM];
-#pragma unroll
-  for (int j = 0; j < PM; ++j) acc[j] = 0.0;
-  for (int64_t r0 = 0; r0 < d; r0 += XTW_RC) {
-#pragma unroll
-    for (int e0 = 0; e0 < NT * XTW_RC; e0 += NT) {
-      const int e = e0 + t;
-      const int cc = e / XTW_RC, rr = e % XTW_RC;
-      const int64_t cg = c0 + cc, r = r0 + rr;
-      xs[rr][cc] = (cg < n && r < d) ? ldx(X, cg * ld + r) : 0.0;
+// FP64 matrix-core tiles.  v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; its result register v holds D[4*v + l/16][l%16].
+// The K index is permuted so that, over four consecutive instructions
+// s = 0..3, lane l covers K positions 4*(l/16)+s: four consecutive rows of one
+// column, which one vector load fetches.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Four consecutive elements X[r..r+3] of one column, widened to FP64.  VEC:
+// the column base and r are aligned for one vector load; rows >= d read 0.
+template <typename TX, bool VEC>
+__device__ __forceinline__ void load4(const TX* __restrict__ col, int64_t r, int64_t d,
+                                      double* x) {
+  if (VEC && r + 3 < d) {
+    if constexpr (sizeof(TX) == 8) {
+      const double2 a = *reinterpret_cast<const double2*>(col + r);
+      const double2 b = *reinterpret_cast<const double2*>(col + r + 2);
+      x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
+    } else if constexpr (sizeof(TX) == 4) {
+      const float4 a = *reinterpret_cast<const float4*>(col + r);
+      x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+    } else {
+      const uint2 a = *reinterpret_cast<const uint2*>(col + r);
+      x[0] = (double)__uint_as_float(a.x << 16);
+      x[1] = (double)__uint_as_float(a.x & 0xFFFF0000u);
+      x[2] = (double)__uint_as_float(a.y << 16);
+      x[3] = (double)__uint_as_float(a.y & 0xFFFF0000u);
     }
-    __syncthreads();
-    const int rmax = (int)min<int64_t>(XTW_RC, d - r0);
-    for (int rr = 0; rr < rmax; ++rr) {
-      const double xv = xs[rr][t];
-      const double* wr = W + r0 + rr;
+  } else {
 #pragma unroll
-      for (int j = 0; j < PM; ++j)
-        if (j < p) acc[j] = fma(xv, wr[(int64_t)j * d], acc[j]);
-    }
-    __syncthreads();
-  }
-  const int64_t col = c0 + t;
-  if (col < n) {
-#pragma unroll
-    for (int j = 0; j < PM; ++j)
-      if (j < p) T[col * p + j] = acc[j];
+    for (int s = 0; s < 4; ++s) x[s] = (r + s < d) ? ldx(col, r + s) : 0.0;
   }
 }
 
-// Pass, second half: Ypart[split] = X[:, split cols] T[split cols, :].
-// One thread per row; X loads are coalesced along rows, T rows are uniform.
-template <typename TX, int PM>
-__global__ __launch_bounds__(NT) void k_xt(const TX* __restrict__ X, int64_t ld, int64_t d,
-                                           int64_t n, int p, const double* __restrict__ T,
-                                           int64_t cps, double* __restrict__ Ypart) {
-  const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
-  const int split = blockIdx.y;
-  const int64_t c0 = (int64_t)split * cps;
-  const int64_t c1 = min(n, c0 + cps);
-  double acc[PM];
+constexpr int KSTAGE = 8192;   // largest minibatch; its indices are staged in LDS
+
+// Sum the NW waves' accumulators into red (NACC 16x16 tiles) in wave order.
+template <int NW, int NACC>
+__device__ __forceinline__ void waves_to_lds(double* red, const v4d* acc, int q, int li) {
+  const int wave = threadIdx.x / 64;
+  for (int w = 0; w < NW; ++w) {
+    if (wave == w) {
 #pragma unroll
-  for (int j = 0; j < PM; ++j) acc[j] = 0.0;
-  const int64_t rr = row < d ? row : d - 1;
-  for (int64_t i = c0; i < c1; ++i) {
-    const double xv = ldx(X, i * ld + rr);
-    const double* ti = T + i * p;
+      for (int a = 0; a < NACC; ++a)
 #pragma unroll
-    for (int j = 0; j < PM; ++j)
-      if (j < p) acc[j] = fma(xv, ti[j], acc[j]);
-  }
-  if (row < d) {
-    double* out = Ypart + (int64_t)split * p * d;
-#pragma unroll
-    for (int j = 0; j < PM; ++j)
-      if (j < p) out[(int64_t)j * d + row] = acc[j];
+        for (int v = 0; v < 4; ++v) {
+          double& o = red[a * 256 + (4 * v + q) * 16 + li];
+          o = (w == 0 ? 0.0 : o) + acc[a][v];
+        }
+    }
+    __syncthreads();
   }
 }
 
-// out = alpha * sum_split Ypart + beta * A + gamma * B (fixed summation order).
-__global__ __launch_bounds__(NT) void k_reduce_y(const double* __restrict__ Ypart, int nsplit,
+// out[c * PC + 16 nt + j] = scale_c * sum_r X[r, col(c)] M[r, 16 nt + j]
+// for c < ncols, j < 16, nt = blockIdx.y.  col(c) = idx[c] (GATHER) or c.
+// M: d x p, column-major, leading dim d; columns >= p count as zero.  A
+// workgroup owns 16 columns of X and one 16-column slice of M; its NW waves
+// split the rows and prefetch one 16-row block ahead.
+template <typename TX, int NW, bool GATHER, bool VEC>
+__global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64_t ld, int64_t d,
+                                                 int64_t ncols, const int32_t* __restrict__ idx,
+                                                 const double* __restrict__ M, int p,
+                                                 const double* __restrict__ scale,
+                                                 double* __restrict__ out, int PC, bool mvec) {
+  __shared__ double red[256];
+  const int t = threadIdx.x, wave = t / 64, l = t % 64;
+  const int li = l % 16, q = l / 16;
+  const int64_t tile = blockIdx.x;
+  const int nt = blockIdx.y;
+  const int64_t c = tile * 16 + li;
+  const bool cval = c < ncols;
+  int64_t colidx = 0;
+  if (cval) colidx = GATHER ? (int64_t)idx[c] : c;
+  const TX* xcol = X + colidx * ld;
+  const int j = nt * 16 + li;
+  const double* mc = M + (int64_t)(j < p ? j : 0) * d;
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  const int64_t nblk = (d + 15) / 16;
+  const int64_t bpw = (nblk + NW - 1) / NW;
+  const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
+  double xa[4], ma[4];
+  auto fetch = [&](int64_t kb, double* x, double* m) {
+    const int64_t r = kb * 16 + 4 * q;
+    load4<TX, VEC>(xcol, r, d, x);
+    if (!cval) x[0] = x[1] = x[2] = x[3] = 0.0;
+    if (j < p) {
+      if (mvec && r + 3 < d) {
+        const double2 a = *reinterpret_cast<const double2*>(mc + r);
+        const double2 b = *reinterpret_cast<const double2*>(mc + r + 2);
+        m[0] = a.x; m[1] = a.y; m[2] = b.x; m[3] = b.y;
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) m[s] = (r + s < d) ? mc[r + s] : 0.0;
+      }
+    } else {
+      m[0] = m[1] = m[2] = m[3] = 0.0;
+    }
+  };
+  if (b0 < b1) fetch(b0, xa, ma);
+  for (int64_t kb = b0; kb < b1; ++kb) {
+    double xn[4], mn[4];
+    if (kb + 1 < b1) fetch(kb + 1, xn, mn);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = mfma_f64(xa[s], ma[s], acc);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      xa[s] = xn[s];
+      ma[s] = mn[s];
+    }
+  }
+  waves_to_lds<NW, 1>(red, &acc, q, li);
+  for (int e = t; e < 256; e += NW * 64) {
+    const int i = e / 16, jj = e % 16;
+    const int64_t cc = tile * 16 + i;
+    if (cc < ncols) {
+      const double sc = scale ? scale[cc] : 1.0;
+      out[cc * PC + nt * 16 + jj] = sc * red[e];
+    }
+  }
+}
+
+// Pass, second half: part[split][j * d + r] = sum_{c in split} X[r, c] T[c * PC + j]
+// for a tile of 32 rows and all 16 NT columns; the 8 waves split the column range.
+template <typename TX, int NT>
+__global__ __launch_bounds__(512) void k_xt_part(const TX* __restrict__ X, int64_t ld, int64_t d,
+                                                 int64_t n, const double* __restrict__ T, int PC,
+                                                 int p, double* __restrict__ part) {
+  constexpr int NW = 8, MTL = 2;
+  __shared__ double red[MTL * NT * 256];
+  const int t = threadIdx.x, wave = t / 64, l = t % 64;
+  const int lm = l % 16, q = l / 16;
+  const int64_t r0 = (int64_t)blockIdx.x * 16 * MTL;
+  const int split = blockIdx.y, nsplit = gridDim.y;
+  const int64_t kper = (n + nsplit - 1) / nsplit;
+  const int64_t ks = split * kper;
+  const int64_t ke = min(n, ks + kper);
+  v4d acc[MTL * NT];
+#pragma unroll
+  for (int a = 0; a < MTL * NT; ++a) acc[a] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int64_t nblk = ke > ks ? (ke - ks + 15) / 16 : 0;
+  const int64_t bpw = (nblk + NW - 1) / NW;
+  const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
+  int64_t rows[MTL];
+#pragma unroll
+  for (int mt = 0; mt < MTL; ++mt) {
+    const int64_t rr = r0 + mt * 16 + lm;
+    rows[mt] = rr < d ? rr : -1;
+  }
+  double xa[4][MTL], na[4][NT];
+  auto fetch = [&](int64_t kb, double (*x)[MTL], double (*nv)[NT]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t kc = ks + kb * 16 + 4 * q + s;
+      const bool kval = kc < ke;
+      const TX* xcol = X + (kval ? kc : 0) * ld;
+#pragma unroll
+      for (int mt = 0; mt < MTL; ++mt)
+        x[s][mt] = (kval && rows[mt] >= 0) ? ldx(xcol, rows[mt]) : 0.0;
+      const double* nrow = T + (kval ? kc : 0) * PC;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) nv[s][nt] = kval ? nrow[nt * 16 + lm] : 0.0;
+    }
+  };
+  if (b0 < b1) fetch(b0, xa, na);
+  for (int64_t kb = b0; kb < b1; ++kb) {
+    double xn[4][MTL], nn[4][NT];
+    if (kb + 1 < b1) fetch(kb + 1, xn, nn);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int mt = 0; mt < MTL; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt * NT + nt] = mfma_f64(xa[s][mt], na[s][nt], acc[mt * NT + nt]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+      for (int mt = 0; mt < MTL; ++mt) xa[s][mt] = xn[s][mt];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) na[s][nt] = nn[s][nt];
+    }
+  }
+  waves_to_lds<NW, MTL * NT>(red, acc, q, lm);
+  for (int e = t; e < MTL * NT * 256; e += NW * 64) {
+    const int mt = e / (NT * 256), nt = (e / 256) % NT, i = (e / 16) % 16, jj = e % 16;
+    const int64_t r = r0 + mt * 16 + i;
+    const int j = nt * 16 + jj;
+    if (r < d && j < p) part[(int64_t)split * p * d + (int64_t)j * d + r] = red[e];
+  }
+}
+
+// out = alpha * sum_split part + beta * A + gamma * B (fixed summation order).
+__global__ __launch_bounds__(NT) void k_reduce_y(const double* __restrict__ part, int nsplit,
                                                  int64_t cnt, double alpha,
                                                  const double* __restrict__ A, double beta,
                                                  const double* __restrict__ B, double gamma,
@@ -332,141 +459,89 @@ __global__ __launch_bounds__(NT) void k_reduce_y(const double* __restrict__ Ypar
   const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (e >= cnt) return;
   double s = 0.0;
-  for (int k = 0; k < nsplit; ++k) s += Ypart[(int64_t)k * cnt + e];
+  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * cnt + e];
   double v = alpha * s;
   if (A) v += beta * A[e];
   if (B) v += gamma * B[e];
   out[e] = v;
 }
 
-// ---------------------------------------------------------------------------
-// Inner step, part 1.  A workgroup owns NS samples: draws them, then computes
-// C[s, :] = scale_s * x_{i_s}^T Dl with 64-row slabs of the sampled columns
-// and of Dl staged in LDS.
-constexpr int SD_NS = 16;
-template <typename TX, int PM>
-__global__ __launch_bounds__(NT) void k_sample_dot(const TX* __restrict__ X, int64_t ld, int64_t d,
-                                                   int64_t n, int p,
-                                                   const uint64_t* __restrict__ cdf, uint32_t k0,
-                                                   uint32_t k1, uint32_t step, uint32_t epoch,
-                                                   uint32_t word3, int64_t b,
-                                                   const double* __restrict__ Dl,
-                                                   int32_t* __restrict__ idx_out,
-                                                   double* __restrict__ scale_out,
-                                                   double* __restrict__ C) {
-  constexpr int NQ = (PM + 15) / 16;
-  __shared__ int64_t sidx[SD_NS];
-  __shared__ double ssc[SD_NS];
-  __shared__ double xs[64][SD_NS + 1];
-  __shared__ double ds[64][PM + 1];
-  const int t = threadIdx.x;
-  const int64_t s0 = (int64_t)blockIdx.x * SD_NS;
-  if (t < SD_NS) {
-    const int64_t j = s0 + t;
-    if (j < b) {
-      int64_t i;
-      double sc;
-      draw_one(cdf, n, k0, k1, (uint32_t)j, step, epoch, word3, b, &i, &sc);
-      sidx[t] = i;
-      ssc[t] = sc;
-      idx_out[j] = (int32_t)i;
-      scale_out[j] = sc;
-    } else {
-      sidx[t] = -1;
-      ssc[t] = 0.0;
-    }
-  }
+// Inner-step update for a tile of 16 rows and the 16-column slice nt = blockIdx.y:
+// Dl <- Dl - eta (G + lam Dl - U),  U[r, j] = sum_s X[r, idx[s]] C[s * PC + j].
+// The NW waves split the b samples; indices are staged in LDS.
+template <typename TX, int NW>
+__global__ __launch_bounds__(NW * 64) void k_step_update(const TX* __restrict__ X, int64_t ld,
+                                                         int64_t d, int64_t b,
+                                                         const int32_t* __restrict__ idx,
+                                                         const double* __restrict__ C, int PC,
+                                                         int p, const double* __restrict__ G,
+                                                         double* __restrict__ Dl, double lam,
+                                                         double eta) {
+  __shared__ double red[256];
+  __shared__ int sidx[KSTAGE];
+  const int t = threadIdx.x, wave = t / 64, l = t % 64;
+  const int lm = l % 16, q = l / 16;
+  const int64_t r0 = (int64_t)blockIdx.x * 16;
+  const int nt = blockIdx.y;
+  for (int64_t e = t; e < b; e += NW * 64) sidx[e] = idx[e];
   __syncthreads();
-  const int s = t % SD_NS, jg = t / SD_NS;
-  double acc[NQ];
+  const int64_t row = r0 + lm;
+  const bool rval = row < d;
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  const int64_t nblk = (b + 15) / 16;
+  const int64_t bpw = (nblk + NW - 1) / NW;
+  const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
+  double xa[4], na[4];
+  auto fetch = [&](int64_t kb, double* x, double* nv) {
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  for (int64_t r0 = 0; r0 < d; r0 += 64) {
-    for (int e = t; e < 64 * SD_NS; e += NT) {
-      const int rr = e % 64, ss = e / 64;
-      const int64_t r = r0 + rr;
-      const int64_t ci = sidx[ss];
-      xs[rr][ss] = (r < d && ci >= 0) ? ldx(X, ci * ld + r) : 0.0;
+    for (int s = 0; s < 4; ++s) {
+      const int64_t kc = kb * 16 + 4 * q + s;
+      const bool kval = kc < b;
+      const int64_t col = kval ? (int64_t)sidx[kc] : 0;
+      x[s] = (kval && rval) ? ldx(X + col * ld, row) : 0.0;
+      nv[s] = kval ? C[kc * PC + nt * 16 + lm] : 0.0;
     }
-    for (int e = t; e < 64 * PM; e += NT) {
-      const int rr = e % 64, jj = e / 64;
-      const int64_t r = r0 + rr;
-      ds[rr][jj] = (r < d && jj < p) ? Dl[(int64_t)jj * d + r] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int rr = 0; rr < 64; ++rr) {
-      const double xv = xs[rr][s];
+  };
+  if (b0 < b1) fetch(b0, xa, na);
+  for (int64_t kb = b0; kb < b1; ++kb) {
+    double xn[4], nn[4];
+    if (kb + 1 < b1) fetch(kb + 1, xn, nn);
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int j = jg + 16 * q;
-        if (j < PM) acc[q] = fma(xv, ds[rr][j], acc[q]);
-      }
+    for (int s = 0; s < 4; ++s) acc = mfma_f64(xa[s], na[s], acc);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      xa[s] = xn[s];
+      na[s] = nn[s];
     }
-    __syncthreads();
   }
-  if (s0 + s < b) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int j = jg + 16 * q;
-      if (j < p) C[(s0 + s) * p + j] = acc[q] * ssc[s];
+  waves_to_lds<NW, 1>(red, &acc, q, lm);
+  for (int e = t; e < 256; e += NW * 64) {
+    const int i = e / 16, jj = e % 16;
+    const int64_t r = r0 + i;
+    const int j = nt * 16 + jj;
+    if (r < d && j < p) {
+      const int64_t o = (int64_t)j * d + r;
+      const double dl = Dl[o];
+      Dl[o] = dl - eta * (G[o] + lam * dl - red[e]);
     }
   }
 }
 
-// Inner step, part 2.  A workgroup owns 16 rows of Dl and sums
-// X[rows, i_s] C[s, :] over all b samples, 64 samples at a time through LDS.
-constexpr int UP_RT = 16;
-template <typename TX, int PM>
-__global__ __launch_bounds__(NT) void k_update(const TX* __restrict__ X, int64_t ld, int64_t d,
-                                               int p, int64_t b, const int32_t* __restrict__ idx,
-                                               const double* __restrict__ C,
-                                               const double* __restrict__ G,
-                                               double* __restrict__ Dl, double lam, double eta) {
-  constexpr int NQ = (PM + 15) / 16;
-  __shared__ double xs[64][UP_RT + 1];
-  __shared__ double cs[64][PM + 1];
-  const int t = threadIdx.x;
-  const int r = t % UP_RT, jg = t / UP_RT;
-  const int64_t r0 = (int64_t)blockIdx.x * UP_RT;
-  double acc[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  for (int64_t s0 = 0; s0 < b; s0 += 64) {
-    for (int e = t; e < 64 * UP_RT; e += NT) {
-      const int ss = e / UP_RT, rr = e % UP_RT;
-      const int64_t s = s0 + ss, row = r0 + rr;
-      xs[ss][rr] = (s < b && row < d) ? ldx(X, (int64_t)idx[s] * ld + row) : 0.0;
-    }
-    for (int e = t; e < 64 * PM; e += NT) {
-      const int ss = e / PM, jj = e % PM;
-      const int64_t s = s0 + ss;
-      cs[ss][jj] = (s < b && jj < p) ? C[s * p + jj] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int ss = 0; ss < 64; ++ss) {
-      const double xv = xs[ss][r];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int j = jg + 16 * q;
-        if (j < PM) acc[q] = fma(xv, cs[ss][j], acc[q]);
-      }
-    }
-    __syncthreads();
-  }
-  const int64_t row = r0 + r;
-  if (row < d) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int j = jg + 16 * q;
-      if (j < p) {
-        const int64_t e = (int64_t)j * d + row;
-        const double dl = Dl[e];
-        Dl[e] = dl - eta * (G[e] + lam * dl - acc[q]);
-      }
-    }
-  }
+// All draws of `steps` consecutive inner steps (from step t0) of one epoch:
+// idx[(t - t0) * b + j], scale[...] for draw j of step t.
+__global__ __launch_bounds__(NT) void k_draw(int64_t n, const uint64_t* __restrict__ cdf,
+                                             uint32_t k0, uint32_t k1, uint32_t t0, int64_t steps,
+                                             uint32_t epoch, uint32_t word3, int64_t b,
+                                             int32_t* __restrict__ idx,
+                                             double* __restrict__ scale) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= steps * b) return;
+  const int64_t t = e / b, j = e % b;
+  int64_t i;
+  double sc;
+  draw_one(cdf, n, k0, k1, (uint32_t)j, t0 + (uint32_t)t, epoch, word3, b, &i, &sc);
+  idx[e] = (int32_t)i;
+  scale[e] = sc;
 }
 
 __global__ __launch_bounds__(NT) void k_sample_only(int64_t n, const uint64_t* __restrict__ cdf,
@@ -937,59 +1012,96 @@ hipError_t gaussian(double* S, int64_t d, int p, uint64_t seed, uint32_t word3, 
   return hipGetLastError();
 }
 
-int pass_nsplit(int64_t d, int64_t n) {
-  const int64_t rowtiles = (d + NT - 1) / NT;
-  int64_t ns = (1024 + rowtiles - 1) / rowtiles;
-  const int64_t maxs = (n + 63) / 64;
-  if (ns > maxs) ns = maxs;
-  if (ns < 1) ns = 1;
-  return (int)ns;
+#define LR_DISPATCH_NT(p, NTV, ...)   \
+  if ((p) <= 16) {                    \
+    constexpr int NTV = 1;            \
+    __VA_ARGS__;                      \
+  } else if ((p) <= 32) {             \
+    constexpr int NTV = 2;            \
+    __VA_ARGS__;                      \
+  } else if ((p) <= 48) {             \
+    constexpr int NTV = 3;            \
+    __VA_ARGS__;                      \
+  } else if ((p) <= 64) {             \
+    constexpr int NTV = 4;            \
+    __VA_ARGS__;                      \
+  } else {                            \
+    return hipErrorInvalidValue;      \
+  }
+
+int pad16(int p) { return ((p + 15) / 16) * 16; }
+
+// Vector loads of four consecutive rows need the column start aligned.
+static bool x_vec_ok(const XView& X) {
+  const uintptr_t base = (uintptr_t)X.v;
+  if (X.dt == 0) return X.ld % 2 == 0 && base % 16 == 0;
+  if (X.dt == 1) return X.ld % 4 == 0 && base % 16 == 0;
+  return X.ld % 4 == 0 && base % 8 == 0;
 }
 
-hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, hipStream_t st) {
-  LR_DISPATCH_DT(X.dt, TX,
-                 LR_DISPATCH_PM(p, PM,
-                                k_xtw<TX, PM><<<nblocks(X.n), NT, 0, st>>>(
-                                    (const TX*)X.v, X.ld, X.d, X.n, p, W, T)));
+static int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+int pass_nsplit(int64_t d, int64_t n) {
+  const int64_t tiles = (d + 31) / 32;
+  return (int)clampi((2048 + tiles - 1) / tiles, 1, std::max<int64_t>(1, (n + 127) / 128));
+}
+
+template <int NW, bool GATHER>
+static hipError_t launch_xtm(const XView& X, int64_t ncols, const int32_t* idx, const double* M,
+                             int p, const double* scale, double* out, int PC, hipStream_t st) {
+  const bool vec = x_vec_ok(X);
+  const bool mvec = X.d % 2 == 0 && (uintptr_t)M % 16 == 0;  // M columns start 16-B aligned
+  dim3 grid((unsigned)((ncols + 15) / 16), (unsigned)((p + 15) / 16));
+  LR_DISPATCH_DT(X.dt, TX, {
+    if (vec)
+      k_xtm<TX, NW, GATHER, true><<<grid, NW * 64, 0, st>>>((const TX*)X.v, X.ld, X.d, ncols, idx,
+                                                            M, p, scale, out, PC, mvec);
+    else
+      k_xtm<TX, NW, GATHER, false><<<grid, NW * 64, 0, st>>>((const TX*)X.v, X.ld, X.d, ncols,
+                                                             idx, M, p, scale, out, PC, mvec);
+  });
   return hipGetLastError();
 }
 
-hipError_t pass_xt(const XView& X, const double* T, int p, const PassBufs& pb, double alpha,
-                   const double* A, double beta, const double* B, double gamma, double* out,
-                   hipStream_t st) {
-  const int64_t cps = (X.n + pb.nsplit - 1) / pb.nsplit;
-  dim3 grid(nblocks(X.d), (unsigned)pb.nsplit);
-  LR_DISPATCH_DT(X.dt, TX,
-                 LR_DISPATCH_PM(p, PM,
-                                k_xt<TX, PM><<<grid, NT, 0, st>>>((const TX*)X.v, X.ld, X.d, X.n,
-                                                                  p, T, cps, pb.Ypart)));
+hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, hipStream_t st) {
+  if (p > 64) return hipErrorInvalidValue;
+  return launch_xtm<8, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st);
+}
+
+hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBufs& pb,
+                   double alpha, const double* A, double beta, const double* B, double gamma,
+                   double* out, hipStream_t st) {
+  dim3 grid((unsigned)((X.d + 31) / 32), (unsigned)pb.nsplit);
+  LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV,
+      k_xt_part<TX, NTV><<<grid, 512, 0, st>>>((const TX*)X.v, X.ld, X.d, X.n, T, PC, p,
+                                                pb.Ypart)));
   const int64_t cnt = X.d * p;
   k_reduce_y<<<nblocks(cnt), NT, 0, st>>>(pb.Ypart, pb.nsplit, cnt, alpha, A, beta, B, gamma, out);
   return hipGetLastError();
 }
 
-hipError_t step_sample_dot(const XView& X, int p, const uint64_t* cdf, uint64_t seed,
-                           uint32_t step, uint32_t epoch, uint32_t word3, int64_t b,
-                           const double* Dl, int32_t* idx, double* scale, double* C,
-                           hipStream_t st) {
-  const unsigned grid = nblocks(b, SD_NS);
-  LR_DISPATCH_DT(X.dt, TX,
-                 LR_DISPATCH_PM(p, PM,
-                                k_sample_dot<TX, PM><<<grid, NT, 0, st>>>(
-                                    (const TX*)X.v, X.ld, X.d, X.n, p, cdf, (uint32_t)seed,
-                                    (uint32_t)(seed >> 32), step, epoch, word3, b, Dl, idx,
-                                    scale, C)));
+hipError_t draw_chunk(int64_t n, const uint64_t* cdf, uint64_t seed, uint32_t t0, int64_t steps,
+                      uint32_t epoch, uint32_t word3, int64_t b, int32_t* idx, double* scale,
+                      hipStream_t st) {
+  k_draw<<<nblocks(steps * b), NT, 0, st>>>(n, cdf, (uint32_t)seed, (uint32_t)(seed >> 32), t0,
+                                             steps, epoch, word3, b, idx, scale);
   return hipGetLastError();
 }
 
+hipError_t step_dot(const XView& X, int p, int64_t b, const int32_t* idx, const double* scale,
+                    const double* Dl, double* C, int PC, hipStream_t st) {
+  if (p > 64) return hipErrorInvalidValue;
+  return launch_xtm<16, true>(X, b, idx, Dl, p, scale, C, PC, st);
+}
+
 hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, const double* C,
-                       const double* G, double* Dl, double lam, double eta, hipStream_t st) {
-  const unsigned grid = nblocks(X.d, UP_RT);
+                       int PC, const double* G, double* Dl, double lam, double eta,
+                       hipStream_t st) {
+  if (p > 64 || b > KSTAGE) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((X.d + 15) / 16), (unsigned)((p + 15) / 16));
   LR_DISPATCH_DT(X.dt, TX,
-                 LR_DISPATCH_PM(p, PM,
-                                k_update<TX, PM><<<grid, NT, 0, st>>>((const TX*)X.v, X.ld, X.d,
-                                                                      p, b, idx, C, G, Dl, lam,
-                                                                      eta)));
+      k_step_update<TX, 16><<<grid, 1024, 0, st>>>((const TX*)X.v, X.ld, X.d, b, idx, C, PC, p,
+                                                   G, Dl, lam, eta));
   return hipGetLastError();
 }
 

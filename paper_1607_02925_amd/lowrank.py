@@ -54,7 +54,8 @@ class lr_report(ctypes.Structure):
                 ("passes", ctypes.c_int64), ("steps", ctypes.c_int64),
                 ("last_change", ctypes.c_double), ("ms_pass_total", ctypes.c_double),
                 ("ms_steps_total", ctypes.c_double), ("timed_passes", ctypes.c_int64),
-                ("timed_steps", ctypes.c_int64)]
+                ("timed_steps", ctypes.c_int64), ("ms_sample_dot_probe", ctypes.c_double),
+                ("ms_update_probe", ctypes.c_double), ("probes", ctypes.c_int64)]
 
 
 # name -> (restype, argtypes); the full exported surface of include/lowrank.h
@@ -285,4 +286,6 @@ def report_dict(rep, p):
         "steps": rep.steps, "last_change": rep.last_change,
         "ms_pass_total": rep.ms_pass_total, "ms_steps_total": rep.ms_steps_total,
         "timed_passes": rep.timed_passes, "timed_steps": rep.timed_steps,
+        "ms_sample_dot_probe": rep.ms_sample_dot_probe, "ms_update_probe": rep.ms_update_probe,
+        "probes": rep.probes,
     }
