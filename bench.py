@@ -8,8 +8,10 @@ sigma_i = 4 (i - 10)^-0.8 beyond, N(0, 1e-4^2) noise; k = 10, p = 20,
 eps = 1e-4).  Prints one JSON line.
 
 Modes for profiler runs: --mode solve (default), --mode pass (only the
-X (X^T W) pass, --steps times), --mode copy (a device copy of the same bytes as
-X, used to calibrate HBM byte counters).
+X (X^T W) pass, --steps times), --mode epoch (--steps inner-solver epochs of
+the solve's own schedule, each one warm-start pass, m inner steps and a
+residual pass), --mode copy (a device copy of the same bytes as X, used to
+calibrate HBM byte counters).
 """
 import argparse
 import json
@@ -36,7 +38,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="solve", choices=["solve", "pass", "copy"])
+    ap.add_argument("--mode", default="solve", choices=["solve", "pass", "epoch", "copy"])
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
@@ -137,6 +139,22 @@ def main():
         dt = (time.time() - t) / args.steps
         print(json.dumps({"mode": "pass", "ms": dt * 1e3, "x_bytes": x_bytes,
                           "GBps_alg": x_bytes / dt / 1e9}), flush=True)
+        return
+
+    if args.mode == "epoch":
+        # schedule of the same workload (shift 101.647, b 2048, m 124 for this seed)
+        lam, eta, m, b = 101.64710238615051, 0.009837925024862453, 124, 2048
+        plan.prepare()
+        S = torch.linalg.qr(torch.randn((d, p), dtype=torch.float64, device=dev))[0]
+        plan.svrg_solve(S, lam, eta, m, b, 1, 1)
+        torch.cuda.synchronize()
+        t = time.time()
+        for i in range(args.steps):
+            plan.svrg_solve(S, lam, eta, m, b, 2 + i, 1)
+        torch.cuda.synchronize()
+        dt = (time.time() - t) / args.steps
+        print(json.dumps({"mode": "epoch", "ms": dt * 1e3, "m": m, "b": b,
+                          "ms_per_step_incl_passes": dt * 1e3 / m}), flush=True)
         return
 
     for i in range(args.warmup):

@@ -292,11 +292,89 @@ __device__ __forceinline__ void load4(const TX* __restrict__ col, int64_t r, int
   }
 }
 
+// Four consecutive column elements kept in the storage type until use, so
+// that a prefetch group costs 4 (f32), 2 (bf16) or 8 (f64) registers.
+template <typename TX>
+struct Raw4;
+template <>
+struct Raw4<double> {
+  double v[4];
+  __device__ __forceinline__ double get(int s) const { return v[s]; }
+  __device__ __forceinline__ void zero() { v[0] = v[1] = v[2] = v[3] = 0.0; }
+};
+template <>
+struct Raw4<float> {
+  float v[4];
+  __device__ __forceinline__ double get(int s) const { return (double)v[s]; }
+  __device__ __forceinline__ void zero() { v[0] = v[1] = v[2] = v[3] = 0.0f; }
+};
+template <>
+struct Raw4<uint16_t> {
+  uint32_t w[2];  // element 2i in the low half of w[i], 2i+1 in the high half
+  __device__ __forceinline__ double get(int s) const {
+    const uint32_t x = w[s >> 1];
+    return (double)__uint_as_float((s & 1) ? (x & 0xFFFF0000u) : (x << 16));
+  }
+  __device__ __forceinline__ void zero() { w[0] = w[1] = 0u; }
+};
+
+template <typename TX, bool VEC>
+__device__ __forceinline__ void load4raw(const TX* __restrict__ col, int64_t r, int64_t d,
+                                         Raw4<TX>& o) {
+  if (VEC && r + 3 < d) {
+    if constexpr (sizeof(TX) == 8) {
+      const double2 a = *reinterpret_cast<const double2*>(col + r);
+      const double2 b = *reinterpret_cast<const double2*>(col + r + 2);
+      o.v[0] = a.x; o.v[1] = a.y; o.v[2] = b.x; o.v[3] = b.y;
+    } else if constexpr (sizeof(TX) == 4) {
+      const float4 a = *reinterpret_cast<const float4*>(col + r);
+      o.v[0] = a.x; o.v[1] = a.y; o.v[2] = a.z; o.v[3] = a.w;
+    } else {
+      const uint2 a = *reinterpret_cast<const uint2*>(col + r);
+      o.w[0] = a.x; o.w[1] = a.y;
+    }
+  } else {
+    if constexpr (sizeof(TX) == 2) {
+      uint32_t h[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) h[s] = (r + s < d) ? (uint32_t)col[r + s] : 0u;
+      o.w[0] = h[0] | (h[1] << 16);
+      o.w[1] = h[2] | (h[3] << 16);
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) o.v[s] = (r + s < d) ? col[r + s] : (TX)0;
+    }
+  }
+}
+
 constexpr int KSTAGE = 8192;   // largest minibatch; its indices are staged in LDS
 
-// Sum the NW waves' accumulators into red (NACC 16x16 tiles) in wave order.
+// Sum the NW waves' accumulators (NACC 16x16 tiles each) into red[0 .. NACC*256):
+// every wave writes its own slot of slots[NW][NACC*256], one barrier, then the
+// sum over waves in wave order (so the result does not depend on timing).
 template <int NW, int NACC>
-__device__ __forceinline__ void waves_to_lds(double* red, const v4d* acc, int q, int li) {
+__device__ __forceinline__ void waves_to_lds(double* red, double* slots, const v4d* acc, int q,
+                                             int li) {
+  const int t = threadIdx.x, wave = t / 64;
+  double* mine = slots + wave * (NACC * 256);
+#pragma unroll
+  for (int a = 0; a < NACC; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) mine[a * 256 + (4 * v + q) * 16 + li] = acc[a][v];
+  __syncthreads();
+  for (int e = t; e < NACC * 256; e += NW * 64) {
+    double s = slots[e];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s += slots[w * (NACC * 256) + e];
+    red[e] = s;
+  }
+  __syncthreads();
+}
+
+// Same sum with a single NACC*256 buffer, accumulated one wave at a time in
+// wave order (NW barriers; for kernels whose slots would not fit in LDS).
+template <int NW, int NACC>
+__device__ __forceinline__ void waves_to_lds_seq(double* red, const v4d* acc, int q, int li) {
   const int wave = threadIdx.x / 64;
   for (int w = 0; w < NW; ++w) {
     if (wave == w) {
@@ -312,85 +390,103 @@ __device__ __forceinline__ void waves_to_lds(double* red, const v4d* acc, int q,
   }
 }
 
-// out[c * PC + 16 nt + j] = scale_c * sum_r X[r, col(c)] M[r, 16 nt + j]
-// for c < ncols, j < 16, nt = blockIdx.y.  col(c) = idx[c] (GATHER) or c.
-// M: d x p, column-major, leading dim d; columns >= p count as zero.  A
-// workgroup owns 16 columns of X and one 16-column slice of M; its NW waves
-// split the rows and prefetch one 16-row block ahead.
-template <typename TX, int NW, bool GATHER, bool VEC>
+// out[c * PC + 16 (NTW y + u) + j] = scale_c * sum_r X[r, col(c)] M[r, 16 (NTW y + u) + j]
+// for c < ncols, j < 16, u < NTW, y = blockIdx.y.  col(c) = idx[c] (GATHER)
+// or c.  M: d x p, column-major, leading dim d; columns >= p count as zero.
+// A workgroup owns 16 columns of X and NTW 16-column slices of M; its NW
+// waves split the rows.  Each wave issues the loads of G 16-row blocks before
+// it starts their matrix-core work, so G memory latencies overlap.
+template <typename TX, int NW, int NTW, int G, bool GATHER, bool VEC>
 __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64_t ld, int64_t d,
                                                  int64_t ncols, const int32_t* __restrict__ idx,
                                                  const double* __restrict__ M, int p,
                                                  const double* __restrict__ scale,
                                                  double* __restrict__ out, int PC, bool mvec) {
-  __shared__ double red[256];
+  __shared__ double red[NTW * 256];
+  __shared__ double slots[NW * NTW * 256];
   const int t = threadIdx.x, wave = t / 64, l = t % 64;
   const int li = l % 16, q = l / 16;
   const int64_t tile = blockIdx.x;
-  const int nt = blockIdx.y;
+  const int nt0 = blockIdx.y * NTW;
   const int64_t c = tile * 16 + li;
   const bool cval = c < ncols;
   int64_t colidx = 0;
   if (cval) colidx = GATHER ? (int64_t)idx[c] : c;
   const TX* xcol = X + colidx * ld;
-  const int j = nt * 16 + li;
-  const double* mc = M + (int64_t)(j < p ? j : 0) * d;
-  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  const double* mc[NTW];
+  bool jval[NTW];
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) {
+    const int j = (nt0 + u) * 16 + li;
+    jval[u] = j < p;
+    mc[u] = M + (int64_t)(jval[u] ? j : 0) * d;
+  }
+  v4d acc[NTW];
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t nblk = (d + 15) / 16;
   const int64_t bpw = (nblk + NW - 1) / NW;
   const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
-  double xa[4], ma[4];
-  auto fetch = [&](int64_t kb, double* x, double* m) {
-    const int64_t r = kb * 16 + 4 * q;
-    load4<TX, VEC>(xcol, r, d, x);
-    if (!cval) x[0] = x[1] = x[2] = x[3] = 0.0;
-    if (j < p) {
-      if (mvec && r + 3 < d) {
-        const double2 a = *reinterpret_cast<const double2*>(mc + r);
-        const double2 b = *reinterpret_cast<const double2*>(mc + r + 2);
-        m[0] = a.x; m[1] = a.y; m[2] = b.x; m[3] = b.y;
-      } else {
+  for (int64_t g0 = b0; g0 < b1; g0 += G) {
+    Raw4<TX> x[G];
+    double m[G][NTW][4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) m[s] = (r + s < d) ? mc[r + s] : 0.0;
+    for (int i = 0; i < G; ++i) {
+      const int64_t r = (g0 + i) * 16 + 4 * q;
+      const bool bval = g0 + i < b1;
+      if (bval && cval)
+        load4raw<TX, VEC>(xcol, r, d, x[i]);
+      else
+        x[i].zero();
+#pragma unroll
+      for (int u = 0; u < NTW; ++u) {
+        if (bval && jval[u]) {
+          if (mvec && r + 3 < d) {
+            const double2 a = *reinterpret_cast<const double2*>(mc[u] + r);
+            const double2 b = *reinterpret_cast<const double2*>(mc[u] + r + 2);
+            m[i][u][0] = a.x; m[i][u][1] = a.y; m[i][u][2] = b.x; m[i][u][3] = b.y;
+          } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) m[i][u][s] = (r + s < d) ? mc[u][r + s] : 0.0;
+          }
+        } else {
+          m[i][u][0] = m[i][u][1] = m[i][u][2] = m[i][u][3] = 0.0;
+        }
       }
-    } else {
-      m[0] = m[1] = m[2] = m[3] = 0.0;
     }
-  };
-  if (b0 < b1) fetch(b0, xa, ma);
-  for (int64_t kb = b0; kb < b1; ++kb) {
-    double xn[4], mn[4];
-    if (kb + 1 < b1) fetch(kb + 1, xn, mn);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc = mfma_f64(xa[s], ma[s], acc);
+    for (int i = 0; i < G; ++i)
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      xa[s] = xn[s];
-      ma[s] = mn[s];
-    }
+      for (int u = 0; u < NTW; ++u)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[u] = mfma_f64(x[i].get(s), m[i][u][s], acc[u]);
   }
-  waves_to_lds<NW, 1>(red, &acc, q, li);
-  for (int e = t; e < 256; e += NW * 64) {
-    const int i = e / 16, jj = e % 16;
+  waves_to_lds<NW, NTW>(red, slots, acc, q, li);
+  for (int e = t; e < NTW * 256; e += NW * 64) {
+    const int u = e / 256, i = (e / 16) % 16, jj = e % 16;
     const int64_t cc = tile * 16 + i;
-    if (cc < ncols) {
+    if (cc < ncols && (nt0 + u) * 16 < PC) {
       const double sc = scale ? scale[cc] : 1.0;
-      out[cc * PC + nt * 16 + jj] = sc * red[e];
+      out[cc * PC + (nt0 + u) * 16 + jj] = sc * red[e];
     }
   }
 }
 
-// Pass, second half: part[split][j * d + r] = sum_{c in split} X[r, c] T[c * PC + j]
-// for a tile of 32 rows and all 16 NT columns; the 8 waves split the column range.
-template <typename TX, int NT>
+// Pass, second half: part[split][j * d + r] = sum_{c in split} X[r, c] T[c * PC + j].
+// A workgroup owns 64 rows as four 16-row tiles whose rows interleave
+// (tile mt holds rows r0 + 4 i + mt), so each lane fetches four consecutive
+// rows of one column with a single vector load; all 16 NT columns; the 8 waves
+// split the column range and load G column blocks ahead.
+template <typename TX, int NT, int G, bool VEC>
 __global__ __launch_bounds__(512) void k_xt_part(const TX* __restrict__ X, int64_t ld, int64_t d,
                                                  int64_t n, const double* __restrict__ T, int PC,
                                                  int p, double* __restrict__ part) {
-  constexpr int NW = 8, MTL = 2;
+  constexpr int NW = 8, MTL = 4;
   __shared__ double red[MTL * NT * 256];
   const int t = threadIdx.x, wave = t / 64, l = t % 64;
   const int lm = l % 16, q = l / 16;
-  const int64_t r0 = (int64_t)blockIdx.x * 16 * MTL;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int64_t rbase = r0 + 4 * lm;
   const int split = blockIdx.y, nsplit = gridDim.y;
   const int64_t kper = (n + nsplit - 1) / nsplit;
   const int64_t ks = split * kper;
@@ -401,50 +497,37 @@ __global__ __launch_bounds__(512) void k_xt_part(const TX* __restrict__ X, int64
   const int64_t nblk = ke > ks ? (ke - ks + 15) / 16 : 0;
   const int64_t bpw = (nblk + NW - 1) / NW;
   const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
-  int64_t rows[MTL];
+  for (int64_t g0 = b0; g0 < b1; g0 += G) {
+    Raw4<TX> x[G][4];
+    double nv[G][4][NT];
 #pragma unroll
-  for (int mt = 0; mt < MTL; ++mt) {
-    const int64_t rr = r0 + mt * 16 + lm;
-    rows[mt] = rr < d ? rr : -1;
+    for (int i = 0; i < G; ++i)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t kc = ks + (g0 + i) * 16 + 4 * q + s;
+        const bool kval = (g0 + i < b1) && kc < ke;
+        if (kval)
+          load4raw<TX, VEC>(X + kc * ld, rbase, d, x[i][s]);
+        else
+          x[i][s].zero();
+        const double* nrow = T + (kval ? kc : 0) * PC;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) nv[i][s][nt] = kval ? nrow[nt * 16 + lm] : 0.0;
+      }
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int mt = 0; mt < MTL; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            acc[mt * NT + nt] = mfma_f64(x[i][s].get(mt), nv[i][s][nt], acc[mt * NT + nt]);
   }
-  double xa[4][MTL], na[4][NT];
-  auto fetch = [&](int64_t kb, double (*x)[MTL], double (*nv)[NT]) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int64_t kc = ks + kb * 16 + 4 * q + s;
-      const bool kval = kc < ke;
-      const TX* xcol = X + (kval ? kc : 0) * ld;
-#pragma unroll
-      for (int mt = 0; mt < MTL; ++mt)
-        x[s][mt] = (kval && rows[mt] >= 0) ? ldx(xcol, rows[mt]) : 0.0;
-      const double* nrow = T + (kval ? kc : 0) * PC;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) nv[s][nt] = kval ? nrow[nt * 16 + lm] : 0.0;
-    }
-  };
-  if (b0 < b1) fetch(b0, xa, na);
-  for (int64_t kb = b0; kb < b1; ++kb) {
-    double xn[4][MTL], nn[4][NT];
-    if (kb + 1 < b1) fetch(kb + 1, xn, nn);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int mt = 0; mt < MTL; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          acc[mt * NT + nt] = mfma_f64(xa[s][mt], na[s][nt], acc[mt * NT + nt]);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-#pragma unroll
-      for (int mt = 0; mt < MTL; ++mt) xa[s][mt] = xn[s][mt];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) na[s][nt] = nn[s][nt];
-    }
-  }
-  waves_to_lds<NW, MTL * NT>(red, acc, q, lm);
+  waves_to_lds_seq<NW, MTL * NT>(red, acc, q, lm);
   for (int e = t; e < MTL * NT * 256; e += NW * 64) {
     const int mt = e / (NT * 256), nt = (e / 256) % NT, i = (e / 16) % 16, jj = e % 16;
-    const int64_t r = r0 + mt * 16 + i;
+    const int64_t r = r0 + 4 * i + mt;
     const int j = nt * 16 + jj;
     if (r < d && j < p) part[(int64_t)split * p * d + (int64_t)j * d + r] = red[e];
   }
@@ -468,62 +551,74 @@ __global__ __launch_bounds__(NT) void k_reduce_y(const double* __restrict__ part
 
 // Inner-step update for a tile of 16 rows and the 16-column slice nt = blockIdx.y:
 // Dl <- Dl - eta (G + lam Dl - U),  U[r, j] = sum_s X[r, idx[s]] C[s * PC + j].
-// The NW waves split the b samples; indices are staged in LDS.
-template <typename TX, int NW>
+// The NW waves split the b samples (indices staged in LDS) and load G sample
+// blocks ahead.
+template <typename TX, int NW, int G, int PC, int NTW>
 __global__ __launch_bounds__(NW * 64) void k_step_update(const TX* __restrict__ X, int64_t ld,
                                                          int64_t d, int64_t b,
                                                          const int32_t* __restrict__ idx,
-                                                         const double* __restrict__ C, int PC,
-                                                         int p, const double* __restrict__ G,
+                                                         const double* __restrict__ C, int p,
+                                                         const double* __restrict__ Gr,
                                                          double* __restrict__ Dl, double lam,
                                                          double eta) {
-  __shared__ double red[256];
+  __shared__ double red[NTW * 256];
+  __shared__ double slots[NW * NTW * 256];
   __shared__ int sidx[KSTAGE];
   const int t = threadIdx.x, wave = t / 64, l = t % 64;
   const int lm = l % 16, q = l / 16;
   const int64_t r0 = (int64_t)blockIdx.x * 16;
-  const int nt = blockIdx.y;
+  const int nt0 = blockIdx.y * NTW;
+  // the epilogue's operands are fetched now, so their latency overlaps the loop
+  double e_dl[NTW], e_g[NTW];
+  int64_t eo[NTW];
+  bool eval[NTW];
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) {
+    const int e = t + u * NW * 64;
+    const int64_t er = r0 + (e % 256) / 16;
+    const int ej = (nt0 + e / 256) * 16 + e % 16;
+    eval[u] = e < NTW * 256 && er < d && ej < p;
+    eo[u] = eval[u] ? (int64_t)ej * d + er : 0;
+    e_dl[u] = eval[u] ? Dl[eo[u]] : 0.0;
+    e_g[u] = eval[u] ? Gr[eo[u]] : 0.0;
+  }
   for (int64_t e = t; e < b; e += NW * 64) sidx[e] = idx[e];
   __syncthreads();
   const int64_t row = r0 + lm;
   const bool rval = row < d;
-  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  v4d acc[NTW];
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t nblk = (b + 15) / 16;
   const int64_t bpw = (nblk + NW - 1) / NW;
   const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
-  double xa[4], na[4];
-  auto fetch = [&](int64_t kb, double* x, double* nv) {
+  for (int64_t g0 = b0; g0 < b1; g0 += G) {
+    TX x[G][4];
+    double nv[G][4][NTW];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int64_t kc = kb * 16 + 4 * q + s;
-      const bool kval = kc < b;
-      const int64_t col = kval ? (int64_t)sidx[kc] : 0;
-      x[s] = (kval && rval) ? ldx(X + col * ld, row) : 0.0;
-      nv[s] = kval ? C[kc * PC + nt * 16 + lm] : 0.0;
-    }
-  };
-  if (b0 < b1) fetch(b0, xa, na);
-  for (int64_t kb = b0; kb < b1; ++kb) {
-    double xn[4], nn[4];
-    if (kb + 1 < b1) fetch(kb + 1, xn, nn);
+    for (int i = 0; i < G; ++i)
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc = mfma_f64(xa[s], na[s], acc);
+      for (int s = 0; s < 4; ++s) {
+        const int64_t kc = (g0 + i) * 16 + 4 * q + s;
+        const bool kval = (g0 + i < b1) && kc < b;
+        const int64_t col = kval ? (int64_t)sidx[kc] : 0;
+        x[i][s] = (kval && rval) ? X[col * ld + row] : (TX)0;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      xa[s] = xn[s];
-      na[s] = nn[s];
-    }
+        for (int u = 0; u < NTW; ++u)
+          nv[i][s][u] = (kval && (nt0 + u) * 16 < PC) ? C[kc * PC + (nt0 + u) * 16 + lm] : 0.0;
+      }
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int u = 0; u < NTW; ++u) acc[u] = mfma_f64(ldx(&x[i][s], 0), nv[i][s][u], acc[u]);
   }
-  waves_to_lds<NW, 1>(red, &acc, q, lm);
-  for (int e = t; e < 256; e += NW * 64) {
-    const int i = e / 16, jj = e % 16;
-    const int64_t r = r0 + i;
-    const int j = nt * 16 + jj;
-    if (r < d && j < p) {
-      const int64_t o = (int64_t)j * d + r;
-      const double dl = Dl[o];
-      Dl[o] = dl - eta * (G[o] + lam * dl - red[e]);
-    }
+  waves_to_lds<NW, NTW>(red, slots, acc, q, lm);
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) {
+    const int e = t + u * NW * 64;
+    if (eval[u]) Dl[eo[u]] = e_dl[u] - eta * (e_g[u] + lam * e_dl[u] - red[e]);
   }
 }
 
@@ -1042,39 +1137,50 @@ static bool x_vec_ok(const XView& X) {
 static int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 int pass_nsplit(int64_t d, int64_t n) {
-  const int64_t tiles = (d + 31) / 32;
+  const int64_t tiles = (d + 63) / 64;
   return (int)clampi((2048 + tiles - 1) / tiles, 1, std::max<int64_t>(1, (n + 127) / 128));
 }
 
-template <int NW, bool GATHER>
+template <int NW, int NTW, int G, bool GATHER>
 static hipError_t launch_xtm(const XView& X, int64_t ncols, const int32_t* idx, const double* M,
                              int p, const double* scale, double* out, int PC, hipStream_t st) {
   const bool vec = x_vec_ok(X);
   const bool mvec = X.d % 2 == 0 && (uintptr_t)M % 16 == 0;  // M columns start 16-B aligned
-  dim3 grid((unsigned)((ncols + 15) / 16), (unsigned)((p + 15) / 16));
+  const int nt = (p + 15) / 16;
+  dim3 grid((unsigned)((ncols + 15) / 16), (unsigned)((nt + NTW - 1) / NTW));
   LR_DISPATCH_DT(X.dt, TX, {
     if (vec)
-      k_xtm<TX, NW, GATHER, true><<<grid, NW * 64, 0, st>>>((const TX*)X.v, X.ld, X.d, ncols, idx,
-                                                            M, p, scale, out, PC, mvec);
+      k_xtm<TX, NW, NTW, G, GATHER, true><<<grid, NW * 64, 0, st>>>(
+          (const TX*)X.v, X.ld, X.d, ncols, idx, M, p, scale, out, PC, mvec);
     else
-      k_xtm<TX, NW, GATHER, false><<<grid, NW * 64, 0, st>>>((const TX*)X.v, X.ld, X.d, ncols,
-                                                             idx, M, p, scale, out, PC, mvec);
+      k_xtm<TX, NW, NTW, G, GATHER, false><<<grid, NW * 64, 0, st>>>(
+          (const TX*)X.v, X.ld, X.d, ncols, idx, M, p, scale, out, PC, mvec);
   });
   return hipGetLastError();
 }
 
 hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, hipStream_t st) {
-  if (p > 64) return hipErrorInvalidValue;
-  return launch_xtm<8, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st);
+  if (p > 64 || pad16(p) > PC) return hipErrorInvalidValue;
+  if (p > 32) return launch_xtm<8, 4, 2, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st);
+  if (p > 16) return launch_xtm<8, 2, 4, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st);
+  return launch_xtm<8, 1, 4, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st);
 }
 
 hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBufs& pb,
                    double alpha, const double* A, double beta, const double* B, double gamma,
                    double* out, hipStream_t st) {
-  dim3 grid((unsigned)((X.d + 31) / 32), (unsigned)pb.nsplit);
-  LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV,
-      k_xt_part<TX, NTV><<<grid, 512, 0, st>>>((const TX*)X.v, X.ld, X.d, X.n, T, PC, p,
-                                                pb.Ypart)));
+  if (p > 64 || pad16(p) > PC) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((X.d + 63) / 64), (unsigned)pb.nsplit);
+  const bool vec = x_vec_ok(X);
+  LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV, {
+    constexpr int GV = NTV <= 2 ? 2 : 1;
+    if (vec)
+      k_xt_part<TX, NTV, GV, true><<<grid, 512, 0, st>>>((const TX*)X.v, X.ld, X.d, X.n, T, PC, p,
+                                                         pb.Ypart);
+    else
+      k_xt_part<TX, NTV, GV, false><<<grid, 512, 0, st>>>((const TX*)X.v, X.ld, X.d, X.n, T, PC, p,
+                                                          pb.Ypart);
+  }));
   const int64_t cnt = X.d * p;
   k_reduce_y<<<nblocks(cnt), NT, 0, st>>>(pb.Ypart, pb.nsplit, cnt, alpha, A, beta, B, gamma, out);
   return hipGetLastError();
@@ -1090,18 +1196,20 @@ hipError_t draw_chunk(int64_t n, const uint64_t* cdf, uint64_t seed, uint32_t t0
 
 hipError_t step_dot(const XView& X, int p, int64_t b, const int32_t* idx, const double* scale,
                     const double* Dl, double* C, int PC, hipStream_t st) {
-  if (p > 64) return hipErrorInvalidValue;
-  return launch_xtm<16, true>(X, b, idx, Dl, p, scale, C, PC, st);
+  if (p > 64 || pad16(p) > PC) return hipErrorInvalidValue;
+  return launch_xtm<16, 1, 4, true>(X, b, idx, Dl, p, scale, C, PC, st);
 }
 
 hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, const double* C,
                        int PC, const double* G, double* Dl, double lam, double eta,
                        hipStream_t st) {
-  if (p > 64 || b > KSTAGE) return hipErrorInvalidValue;
+  if (p > 64 || b > KSTAGE || pad16(p) != PC) return hipErrorInvalidValue;
+  // one 16-column slice per workgroup: twice the gathers of one slice per
+  // row tile, but twice the workgroups, which this latency-bound step needs
   dim3 grid((unsigned)((X.d + 15) / 16), (unsigned)((p + 15) / 16));
-  LR_DISPATCH_DT(X.dt, TX,
-      k_step_update<TX, 16><<<grid, 1024, 0, st>>>((const TX*)X.v, X.ld, X.d, b, idx, C, PC, p,
-                                                   G, Dl, lam, eta));
+  LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV,
+      k_step_update<TX, 16, 4, 16 * NTV, 1><<<grid, 1024, 0, st>>>(
+          (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta)));
   return hipGetLastError();
 }
 
