@@ -53,6 +53,27 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (pos - lo)
 
 
+def measured_traffic(kernel, workload):
+    """Calibrated HBM bytes per launch of `kernel` from the committed rocprofv3
+    counter summary, or None when the kernels have changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s.md" % workload)
+    src = os.path.join(ROOT, "paper_1607_02925_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if "```json" not in text:
+        return None
+    t = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != t["kernels_sha256"]:
+        return None
+    k = t["per_launch_kib"].get(kernel)
+    if k is None:
+        return None
+    c = t["calibration"]
+    return (k["fetch"] * c["fetch_scale"] + k["write"] * c["write_scale"]) * 1024.0
+
+
 def cpu_baseline(Xt_dev, w, sched, rep):
     """Time the oracle (NumPy FP64) on a bounded sample of the same workload:
     the sampling table, one X(X^T S) pass and one inner-solver epoch at full
@@ -191,8 +212,8 @@ def main():
     t_sdot_total = ms_sdot * rep["steps"]
     t_pass_total = ms_pass * rep["passes"]
     kernels = {
-        "k_update": (t_upd_total, bytes_update, ms_upd),
-        "k_sample_dot": (t_sdot_total, bytes_sdot, ms_sdot),
+        "k_step_update": (t_upd_total, bytes_update, ms_upd),
+        "k_xtm_gathered": (t_sdot_total, bytes_sdot, ms_sdot),
     }
     dom = max(kernels, key=lambda kk: kernels[kk][0])
     _, dbytes, dms = kernels[dom]
@@ -226,7 +247,8 @@ def main():
                   "share_pass": t_pass_total / (total / args.steps * 1e3)},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS if achieved else None,
-                     "traffic": None, "bytes_per_launch": dbytes, "avg_launch_ms": dms},
+                     "traffic": measured_traffic(dom, args.workload),
+                     "bytes_per_launch": dbytes, "avg_launch_ms": dms},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

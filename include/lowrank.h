@@ -140,9 +140,10 @@ typedef struct lr_report {
   double ms_pass_total;           /* timing = 1: summed duration of all passes */
   double ms_steps_total;          /* timing = 1: summed duration of all inner-step loops */
   int64_t timed_passes, timed_steps;
-  double ms_sample_dot_probe;     /* timing = 1: summed duration of one sampled-dot launch
-                                     per epoch (the launch at step m/2) */
-  double ms_update_probe;         /* timing = 1: same for one update launch per epoch */
+  double ms_sample_dot_probe;     /* timing = 1: summed execution time of one sampled-dot
+                                     kernel per epoch (step m/2), from start/stop events
+                                     attached to that launch */
+  double ms_update_probe;         /* timing = 1: same for one update kernel per epoch */
   int64_t probes;                 /* number of epochs probed */
 } lr_report;
 

@@ -69,7 +69,7 @@ struct lr_plan_s {
   int *dinfo = nullptr, *dbad = nullptr;
   double* hpin = nullptr;
   lr::PassBufs pb{};
-  hipEvent_t ev[7] = {};
+  hipEvent_t ev[8] = {};
 
   bool prepared = false;
   double fro2 = 0;
@@ -208,11 +208,15 @@ struct lr_plan_s {
         for (int64_t t = t0; t < t0 + nst; ++t) {
           const bool probe = opt.timing && t == tprobe;
           const int32_t* it = idx + (t - t0) * b;
-          if (probe) LR_HIP(hipEventRecord(ev[4], st));
-          LR_HIP(lr::step_dot(X, p, b, it, scale + (t - t0) * b, Dl, C, PC, st));
-          if (probe) LR_HIP(hipEventRecord(ev[5], st));
-          LR_HIP(lr::step_update(X, p, b, it, C, PC, G, Dl, lam, eta, st));
-          if (probe) LR_HIP(hipEventRecord(ev[6], st));
+          lr::Probe pd, pu;
+          if (probe) {
+            pd.start = ev[4];
+            pd.stop = ev[5];
+            pu.start = ev[6];
+            pu.stop = ev[7];
+          }
+          LR_HIP(lr::step_dot(X, p, b, it, scale + (t - t0) * b, Dl, C, PC, st, pd));
+          LR_HIP(lr::step_update(X, p, b, it, C, PC, G, Dl, lam, eta, st, pu));
         }
       }
       if (opt.timing) LR_HIP(hipEventRecord(ev[1], st));
@@ -234,7 +238,7 @@ struct lr_plan_s {
         rep.timed_passes += 1;
         LR_HIP(hipEventElapsedTime(&ms, ev[4], ev[5]));
         rep.ms_sample_dot_probe += ms;
-        LR_HIP(hipEventElapsedTime(&ms, ev[5], ev[6]));
+        LR_HIP(hipEventElapsedTime(&ms, ev[6], ev[7]));
         rep.ms_update_probe += ms;
         rep.probes += 1;
       }
@@ -533,7 +537,7 @@ lr_status lowrank_plan(lr_plan* out, const lr_matrix* Xm, int k, int p, double e
     pl->hpin = nullptr;
     s = fail(LR_ENOMEM, "pinned host allocation failed");
   }
-  for (int i = 0; s == LR_OK && i < 7; ++i)
+  for (int i = 0; s == LR_OK && i < 8; ++i)
     if (hipEventCreate(&pl->ev[i]) != hipSuccess) s = fail(LR_EDEVICE, "hipEventCreate failed");
   if (s != LR_OK) {
     delete pl;

@@ -8,6 +8,11 @@
 
 namespace lr {
 
+// Optional start/stop events that time one kernel launch exactly.
+struct Probe {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 struct XView {
   const void* v;
   int64_t d, n, ld;
@@ -32,10 +37,11 @@ struct PassBufs {
 };
 int pad16(int p);
 int pass_nsplit(int64_t d, int64_t n);
-hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, hipStream_t st);
+hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, hipStream_t st,
+                    const Probe& pr = Probe());
 hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBufs& pb,
                    double alpha, const double* A, double beta, const double* B, double gamma,
-                   double* out, hipStream_t st);
+                   double* out, hipStream_t st, const Probe& pr = Probe());
 
 // Column draws of `steps` inner steps starting at step t0 of one epoch:
 // idx/scale[(t - t0) * b + j].
@@ -44,11 +50,12 @@ hipError_t draw_chunk(int64_t n, const uint64_t* cdf, uint64_t seed, uint32_t t0
                       hipStream_t st);
 // Inner step, part 1: C = diag(scale) X_B^T Dl   (C: b x PC row-major).
 hipError_t step_dot(const XView& X, int p, int64_t b, const int32_t* idx, const double* scale,
-                    const double* Dl, double* C, int PC, hipStream_t st);
+                    const double* Dl, double* C, int PC, hipStream_t st,
+                    const Probe& pr = Probe());
 // Inner step, part 2: Dl <- Dl - eta (G + lam Dl - X_B C).  b <= 8192.
 hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, const double* C,
                        int PC, const double* G, double* Dl, double lam, double eta,
-                       hipStream_t st);
+                       hipStream_t st, const Probe& pr = Probe());
 // Draw only (for testing the sampler).
 hipError_t sample_only(int64_t n, const uint64_t* cdf, uint64_t seed, uint32_t step,
                        uint32_t epoch, uint32_t word3, int64_t b, int32_t* idx, double* scale,

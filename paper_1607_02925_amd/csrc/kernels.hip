@@ -3,6 +3,8 @@
 // widened on load.  See kernels.h for the contract of each launcher.
 #include "kernels.h"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 
 #include <algorithm>
@@ -1039,6 +1041,15 @@ inline unsigned nblocks(int64_t count, int per = NT) {
 
 }  // namespace
 
+// Launch a kernel; with probe events, time exactly this kernel's execution.
+template <typename K, typename... A>
+static void launch(K kernel, dim3 grid, dim3 block, hipStream_t st, const Probe& pr, A... args) {
+  if (pr.start)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, pr.start, pr.stop, 0, args...);
+  else
+    kernel<<<grid, block, 0, st>>>(args...);
+}
+
 #define LR_DISPATCH_DT(dt, TX, ...)   \
   switch (dt) {                       \
     case 0: {                         \
@@ -1143,43 +1154,45 @@ int pass_nsplit(int64_t d, int64_t n) {
 
 template <int NW, int NTW, int G, bool GATHER>
 static hipError_t launch_xtm(const XView& X, int64_t ncols, const int32_t* idx, const double* M,
-                             int p, const double* scale, double* out, int PC, hipStream_t st) {
+                             int p, const double* scale, double* out, int PC, hipStream_t st,
+                             const Probe& pr) {
   const bool vec = x_vec_ok(X);
   const bool mvec = X.d % 2 == 0 && (uintptr_t)M % 16 == 0;  // M columns start 16-B aligned
   const int nt = (p + 15) / 16;
   dim3 grid((unsigned)((ncols + 15) / 16), (unsigned)((nt + NTW - 1) / NTW));
   LR_DISPATCH_DT(X.dt, TX, {
     if (vec)
-      k_xtm<TX, NW, NTW, G, GATHER, true><<<grid, NW * 64, 0, st>>>(
-          (const TX*)X.v, X.ld, X.d, ncols, idx, M, p, scale, out, PC, mvec);
+      launch(k_xtm<TX, NW, NTW, G, GATHER, true>, grid, dim3(NW * 64), st, pr, (const TX*)X.v,
+             X.ld, X.d, ncols, idx, M, p, scale, out, PC, mvec);
     else
-      k_xtm<TX, NW, NTW, G, GATHER, false><<<grid, NW * 64, 0, st>>>(
-          (const TX*)X.v, X.ld, X.d, ncols, idx, M, p, scale, out, PC, mvec);
+      launch(k_xtm<TX, NW, NTW, G, GATHER, false>, grid, dim3(NW * 64), st, pr, (const TX*)X.v,
+             X.ld, X.d, ncols, idx, M, p, scale, out, PC, mvec);
   });
   return hipGetLastError();
 }
 
-hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, hipStream_t st) {
+hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, hipStream_t st,
+                    const Probe& pr) {
   if (p > 64 || pad16(p) > PC) return hipErrorInvalidValue;
-  if (p > 32) return launch_xtm<8, 4, 2, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st);
-  if (p > 16) return launch_xtm<8, 2, 4, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st);
-  return launch_xtm<8, 1, 4, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st);
+  if (p > 32) return launch_xtm<8, 4, 2, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st, pr);
+  if (p > 16) return launch_xtm<8, 2, 4, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st, pr);
+  return launch_xtm<8, 1, 4, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st, pr);
 }
 
 hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBufs& pb,
                    double alpha, const double* A, double beta, const double* B, double gamma,
-                   double* out, hipStream_t st) {
+                   double* out, hipStream_t st, const Probe& pr) {
   if (p > 64 || pad16(p) > PC) return hipErrorInvalidValue;
   dim3 grid((unsigned)((X.d + 63) / 64), (unsigned)pb.nsplit);
   const bool vec = x_vec_ok(X);
   LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV, {
     constexpr int GV = NTV <= 2 ? 2 : 1;
     if (vec)
-      k_xt_part<TX, NTV, GV, true><<<grid, 512, 0, st>>>((const TX*)X.v, X.ld, X.d, X.n, T, PC, p,
-                                                         pb.Ypart);
+      launch(k_xt_part<TX, NTV, GV, true>, grid, dim3(512), st, pr, (const TX*)X.v, X.ld, X.d,
+             X.n, T, PC, p, pb.Ypart);
     else
-      k_xt_part<TX, NTV, GV, false><<<grid, 512, 0, st>>>((const TX*)X.v, X.ld, X.d, X.n, T, PC, p,
-                                                          pb.Ypart);
+      launch(k_xt_part<TX, NTV, GV, false>, grid, dim3(512), st, pr, (const TX*)X.v, X.ld, X.d,
+             X.n, T, PC, p, pb.Ypart);
   }));
   const int64_t cnt = X.d * p;
   k_reduce_y<<<nblocks(cnt), NT, 0, st>>>(pb.Ypart, pb.nsplit, cnt, alpha, A, beta, B, gamma, out);
@@ -1195,21 +1208,21 @@ hipError_t draw_chunk(int64_t n, const uint64_t* cdf, uint64_t seed, uint32_t t0
 }
 
 hipError_t step_dot(const XView& X, int p, int64_t b, const int32_t* idx, const double* scale,
-                    const double* Dl, double* C, int PC, hipStream_t st) {
+                    const double* Dl, double* C, int PC, hipStream_t st, const Probe& pr) {
   if (p > 64 || pad16(p) > PC) return hipErrorInvalidValue;
-  return launch_xtm<16, 1, 4, true>(X, b, idx, Dl, p, scale, C, PC, st);
+  return launch_xtm<16, 1, 4, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
 }
 
 hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, const double* C,
                        int PC, const double* G, double* Dl, double lam, double eta,
-                       hipStream_t st) {
+                       hipStream_t st, const Probe& pr) {
   if (p > 64 || b > KSTAGE || pad16(p) != PC) return hipErrorInvalidValue;
   // one 16-column slice per workgroup: twice the gathers of one slice per
   // row tile, but twice the workgroups, which this latency-bound step needs
   dim3 grid((unsigned)((X.d + 15) / 16), (unsigned)((p + 15) / 16));
   LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV,
-      k_step_update<TX, 16, 4, 16 * NTV, 1><<<grid, 1024, 0, st>>>(
-          (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta)));
+      launch(k_step_update<TX, 16, 4, 16 * NTV, 1>, grid, dim3(1024), st, pr, (const TX*)X.v,
+             X.ld, X.d, b, idx, C, p, G, Dl, lam, eta)));
   return hipGetLastError();
 }
 
