@@ -5,7 +5,16 @@ tuning, shift-and-invert subspace iteration with SVRG inner solves, final
 Rayleigh-Ritz) on one resident synthetic matrix: the planted-spectrum
 2048 x 200000 FP32 workload (sigma_1..10 geometric 10 -> 5, sigma_11 = 4.95,
 sigma_i = 4 (i - 10)^-0.8 beyond, N(0, 1e-4^2) noise; k = 10, p = 20,
-eps = 1e-4).  Prints one JSON line.
+eps = 1e-4).  Prints one JSON line; unless --no-serve, the line also carries
+the serving legs described below under "serve".
+
+--mode serve runs the serving form instead: a trace of independent requests
+(d in {256..4096}, n in [4096, 131072] log-uniform, k in 1..16, p = k + 4..16,
+FP32 or BF16 storage, eps = 1e-4, Poisson arrivals at 50/s) through the
+library's request server, once as plain FP32 requests one at a time and once
+continuously batched with each request's own storage type; it reports
+solves/s, p50/p99 latency and whether every FP32 request's result is bitwise
+the same in the batch as alone.
 
 Modes for profiler runs: --mode solve (default), --mode pass (only the
 X (X^T W) pass, --steps times), --mode epoch (--steps inner-solver epochs of
@@ -38,9 +47,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="solve", choices=["solve", "pass", "epoch", "copy"])
+    ap.add_argument("--mode", default="solve",
+                    choices=["solve", "pass", "epoch", "copy", "serve"])
+    ap.add_argument("--requests", type=int, default=512, help="serve: trace length")
+    ap.add_argument("--slots", type=int, default=8, help="serve: concurrent worker slots")
+    ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: HBM budget (GB)")
+    ap.add_argument("--rate", type=float, default=50.0, help="serve: arrivals per second")
+    ap.add_argument("--forms", default="seq,closed,open",
+                    help="serve: comma list of seq (FP32 one at a time), closed, open")
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="solve mode: skip the serving legs of the report")
     return ap.parse_args()
 
 
@@ -110,6 +128,80 @@ def cpu_baseline(Xt_dev, w, sched, rep):
                       % (sched.m, sched.b, rep["passes"], rep["total_epochs"])}
 
 
+def serve_run(reqs, X, slots, budget, open_loop=False):
+    """Push every request of `reqs` (device matrices X[i]) through a server with
+    `slots` worker slots and an HBM budget; closed loop submits all at t = 0,
+    open loop at each request's arrival time.  Returns per-request results."""
+    import torch
+    from paper_1607_02925_amd import lowrank
+    srv = lowrank.Server(budget, slots=slots)
+    torch.cuda.synchronize()
+    tickets = []
+    t0 = time.time()
+    for r, x in zip(reqs, X):
+        if open_loop:
+            delay = r["arrival"] - (time.time() - t0)
+            if delay > 0:
+                time.sleep(delay)
+        tickets.append(srv.submit(x, r["k"], r["p"], r["eps"], sync=False,
+                                  seed=r["solver_seed"]))
+    outs = [srv.wait(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    t_first = min(o[4]["t_submit"] for o in outs)
+    t_last = max(o[4]["t_done"] for o in outs)
+    lat = [o[4]["t_done"] - o[4]["t_submit"] for o in outs]
+    svc = [o[4]["t_done"] - o[4]["t_admit"] for o in outs]
+    bad = [(r["id"], o[0]) for r, o in zip(reqs, outs) if o[0] != 0]
+    pass_bytes = sum(o[3]["passes"] * x.numel() * x.element_size() for o, x in zip(outs, X))
+    res = {"requests": len(reqs), "slots": slots, "budget_bytes": int(budget),
+           "makespan_s": t_last - t_first, "solves_per_s": len(reqs) / (t_last - t_first),
+           "latency_ms": {"p50": percentile(lat, 0.5) * 1e3, "p99": percentile(lat, 0.99) * 1e3,
+                          "max": max(lat) * 1e3},
+           "service_ms": {"p50": percentile(svc, 0.5) * 1e3, "p99": percentile(svc, 0.99) * 1e3},
+           "pass_GBps_alg": pass_bytes / (t_last - t_first) / 1e9,
+           "peak_running": stats["peak_running"], "peak_bytes": stats["peak_bytes"],
+           "failed": bad}
+    return res, outs
+
+
+def serve_bench(args, dev):
+    import torch
+    import workloads
+    reqs = workloads.serving.trace(args.requests, rate=args.rate)
+    t0 = time.time()
+    X32, Xown = [], []
+    for r in reqs:
+        x = workloads.serving.request_data(r, device=dev, storage="f32")
+        X32.append(x)
+        Xown.append(x if r["storage"] == "f32" else x.to(torch.bfloat16))
+    torch.cuda.synchronize()
+    log("serve: generated %d requests (%.1f GB FP32) in %.1fs" %
+        (len(reqs), sum(x.numel() * 4 for x in X32) / 1e9, time.time() - t0))
+    budget = int(args.budget_gb * 1e9)
+    forms = set(args.forms.split(","))
+    out = {"trace": {"requests": len(reqs), "rate_per_s": args.rate,
+                     "f32": sum(r["storage"] == "f32" for r in reqs),
+                     "bf16": sum(r["storage"] == "bf16" for r in reqs)}}
+    seq_outs = closed_outs = None
+    if "seq" in forms:
+        out["fp32_per_request"], seq_outs = serve_run(reqs, X32, 1, budget)
+        log("serve fp32 per-request: %s" % json.dumps(out["fp32_per_request"]))
+    if "closed" in forms:
+        out["batched_closed"], closed_outs = serve_run(reqs, Xown, args.slots, budget)
+        log("serve batched closed loop: %s" % json.dumps(out["batched_closed"]))
+    if "open" in forms:
+        out["batched_open"], _ = serve_run(reqs, Xown, args.slots, budget, open_loop=True)
+        log("serve batched open loop: %s" % json.dumps(out["batched_open"]))
+    if seq_outs is not None and closed_outs is not None:
+        same = [torch.equal(a[1], b[1]) for r, a, b in zip(reqs, seq_outs, closed_outs)
+                if r["storage"] == "f32"]
+        out["f32_bitwise_alone_vs_mix"] = "%d/%d" % (sum(same), len(same))
+        out["speedup_batched_vs_fp32_per_request"] = \
+            out["batched_closed"]["solves_per_s"] / out["fp32_per_request"]["solves_per_s"]
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -123,6 +215,10 @@ def main():
 
     lowrank.load_library()
     dev = "cuda:0"
+    if args.mode == "serve":
+        out = serve_bench(args, dev)
+        print(json.dumps({"mode": "serve", **out}), flush=True)
+        return
     w = dict(workloads.WORKLOADS[args.workload])
     t0 = time.time()
     data = workloads.workload(args.workload, device=dev)
@@ -253,6 +349,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Xt, dict(w, **data), sched, rep)
+    if not args.no_serve:
+        del Xt, data, plan
+        torch.cuda.empty_cache()
+        out["serve"] = serve_bench(args, dev)
     print(json.dumps(out), flush=True)
 
 

@@ -44,6 +44,7 @@ extern "C" {
 
 #define LR_MAX_P 64          /* largest block width p supported */
 #define LR_MAX_SHIFT_ROUNDS 64
+#define LR_MAX_SLOTS 16       /* largest number of worker slots of a server */
 
 typedef enum {
   LR_OK = 0,
@@ -172,6 +173,12 @@ lr_status lowrank_get_schedule(lr_plan plan, lr_schedule* out);
 
 void lowrank_destroy(lr_plan plan);
 
+/* Device workspace in bytes that lowrank_plan (or a server) allocates for
+ * this problem: the n-length sampling table, the n x pad16(p) block X^T W, the
+ * d x p iterates and the minibatch staging.  Same checks as lowrank_plan. */
+lr_status lowrank_plan_bytes(const lr_matrix* X, int k, int p, const lr_options* opt,
+                             size_t* bytes);
+
 /* ---- Single steps of the path, on a plan's X and stream (for testing and
  * measurement).  All matrices FP64 device, column-major, leading dim d. ---- */
 
@@ -207,6 +214,70 @@ lr_status lowrank_op_eigh(lr_plan plan, const double* H, int m, double* vals_out
 lr_status lowrank_op_svrg_solve(lr_plan plan, const double* S, double lambda, double eta,
                                 int64_t m, int64_t b, int32_t solve, int32_t epochs,
                                 double* W_out, double* res_out);
+
+
+/* ---- Request server: continuous batching of independent problems ----
+ *
+ * Many low-rank problems of mixed d, n, k, p and storage type are solved
+ * concurrently on the current device.  Requests queue in submission order; the
+ * request at the head of the queue is admitted as soon as a worker slot is idle
+ * and its whole workspace (lowrank_plan_bytes) fits in the unused part of the
+ * server's HBM budget.  Each slot owns a host thread and a HIP stream, so
+ * admitted requests overlap on the device; each one runs the same kernels in
+ * the same order as lowrank_solve on a plan of its own, so its results are
+ * bitwise the same alone and in any mix.  Requests use the method of
+ * lowrank_solve (Section 3.2, Algorithm "main", q = k branch); the server adds
+ * no approximation.
+ *
+ * Ownership: the caller owns X, U_out and theta_out of every request and keeps
+ * them valid and X unchanged until lowrank_poll or lowrank_wait reports the
+ * request finished.  X must be complete on the device when lowrank_submit is
+ * called (the server's streams do not wait on the caller's).  The server owns
+ * the HBM budget block (allocated once in lowrank_server_create), the slot
+ * streams and threads.  All functions are thread-safe. */
+typedef struct lr_server_s* lr_server;
+
+typedef struct lr_ticket_info {
+  double t_submit, t_admit, t_done;  /* seconds since the server was created */
+  int32_t slot;                      /* worker slot that ran the request */
+  int32_t reserved;
+  uint64_t workspace_bytes;          /* HBM the request held while running */
+} lr_ticket_info;
+
+typedef struct lr_server_stats {
+  int64_t submitted, completed, queued, running;
+  uint64_t budget_bytes, bytes_in_use, peak_bytes;
+  int32_t slots, peak_running;
+  double elapsed;                    /* seconds since the server was created */
+} lr_server_stats;
+
+/* Allocate an HBM budget of hbm_budget_bytes on the current device and start
+ * `slots` worker slots (1..LR_MAX_SLOTS).  LR_ENOMEM if the budget cannot be
+ * allocated, LR_EDEVICE if streams, events or threads cannot be created. */
+lr_status lowrank_server_create(lr_server* out, size_t hbm_budget_bytes, int slots);
+
+/* Queue one problem.  X, k, p, eps, opt as for lowrank_plan (opt may be NULL;
+ * a replay schedule in opt is copied).  U_out: device, d x k FP64 (may be
+ * NULL); theta_out: host, k FP64 (may be NULL).  *ticket identifies the
+ * request.  LR_EINVAL on bad arguments, LR_ENOMEM if the request's workspace
+ * alone exceeds the budget. */
+lr_status lowrank_submit(lr_server srv, const lr_matrix* X, int k, int p, double eps,
+                         const lr_options* opt, double* U_out, double* theta_out,
+                         uint64_t* ticket);
+
+/* LR_EBUSY while the request is queued or running.  Once it has finished:
+ * its lowrank_solve status (LR_OK or the error, with lowrank_last_error set on
+ * this thread), rep and info filled (each may be NULL), and the ticket is
+ * forgotten (a later poll returns LR_EINVAL). */
+lr_status lowrank_poll(lr_server srv, uint64_t ticket, lr_report* rep, lr_ticket_info* info);
+
+/* Block until the request has finished, then as lowrank_poll. */
+lr_status lowrank_wait(lr_server srv, uint64_t ticket, lr_report* rep, lr_ticket_info* info);
+
+lr_status lowrank_server_stats(lr_server srv, lr_server_stats* out);
+
+/* Finish every queued and running request, then release the server. */
+void lowrank_server_destroy(lr_server srv);
 
 #ifdef __cplusplus
 }

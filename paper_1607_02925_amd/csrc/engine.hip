@@ -12,8 +12,10 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
+#include "engine.h"
 #include "kernels.h"
 
 namespace {
@@ -44,6 +46,11 @@ inline uint32_t stream_word(uint32_t tag, uint32_t solve) { return (tag << 28) |
 
 }  // namespace
 
+namespace lr {
+void set_last_error(const std::string& msg) { g_err = msg; }
+std::string last_error() { return g_err; }
+}  // namespace lr
+
 struct lr_plan_s {
   hipStream_t st = nullptr;
   lr::XView X{};
@@ -57,7 +64,9 @@ struct lr_plan_s {
   int PC = 0;                     // padded row stride of T and C
   static constexpr int64_t MCH = 256;  // inner steps whose draws are made in one launch
 
-  std::vector<void*> allocs;
+  void* ws = nullptr;              // the one device block all buffers are carved from
+  bool owns_ws = true;             // false: the block belongs to a server arena
+  bool owns_host = true;           // false: hpin and ev belong to a server slot
   double *w = nullptr, *S = nullptr, *W = nullptr, *Wt = nullptr, *G = nullptr, *Y = nullptr;
   double *Dl = nullptr, *Tm1 = nullptr, *Tm2 = nullptr, *Sest = nullptr, *V = nullptr;
   double *Vprev = nullptr, *T = nullptr, *Ypart = nullptr, *C = nullptr, *scale = nullptr;
@@ -78,23 +87,17 @@ struct lr_plan_s {
   lr_report rep{};
 
   ~lr_plan_s() {
-    for (void* a : allocs) (void)hipFree(a);
-    if (hpin) (void)hipHostFree(hpin);
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
+    if (owns_ws && ws) (void)hipFree(ws);
+    if (owns_host) {
+      if (hpin) (void)hipHostFree(hpin);
+      for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    }
   }
 
-  template <typename Tp>
-  lr_status alloc(Tp** out, size_t count) {
-    void* ptr = nullptr;
-    if (hipMalloc(&ptr, std::max<size_t>(count, 1) * sizeof(Tp)) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(LR_ENOMEM, "device allocation failed");
-    }
-    allocs.push_back(ptr);
-    *out = (Tp*)ptr;
-    return LR_OK;
-  }
+  // Lay every device buffer out in one block at `base` (256-byte aligned
+  // pieces); with base == nullptr only the total size is computed.
+  size_t carve(char* base);
 
   // Copy `bytes` from device to host (synchronises the stream).
   lr_status read(void* host, const void* dev, size_t bytes) {
@@ -404,6 +407,159 @@ lr_status lr_plan_s::solve(double* U_out, double* theta_out, lr_report* out_rep)
   return LR_OK;
 }
 
+size_t lr_plan_s::carve(char* base) {
+  size_t off = 0;
+  auto take = [&](auto** ptr, int64_t count) {
+    off = (off + 255) & ~(size_t)255;
+    if (base) *ptr = reinterpret_cast<std::remove_pointer_t<decltype(ptr)>>(base + off);
+    off += (size_t)std::max<int64_t>(count, 1) * sizeof(**ptr);
+  };
+  const int64_t dp = d * p;
+  const int64_t nbt = (n + 1023) / 1024;
+  const int64_t partn = std::max<int64_t>((int64_t)lr::gram_nblk(std::max(d, n)) * 64 * 64, 1024);
+  take(&w, n);
+  take(&cdf, n + 1);
+  take(&scratch, 3 * nbt + 8);
+  for (double** b : {&S, &W, &Wt, &G, &Y, &Dl, &Tm1, &Tm2, &Sest}) take(b, dp);
+  take(&V, d * k);
+  take(&Vprev, d * k);
+  take(&T, n * PC);
+  take(&Ypart, (int64_t)pb.nsplit * dp);
+  take(&C, bmax * PC);
+  take(&scale, MCH * bmax);
+  take(&idx, MCH * bmax);
+  take(&part, partn);
+  for (double** b : {&H, &Q, &M, &Rinv, &kk1, &kk2}) take(b, 64 * 64);
+  take(&vals, 64);
+  take(&res, 64);
+  take(&dfro2, 1);
+  take(&dnorm, 4);
+  take(&dinfo, 1);
+  take(&dbad, 1);
+  if (base) pb.Ypart = Ypart;
+  return (off + 255) & ~(size_t)255;
+}
+
+namespace lr {
+
+lr_status plan_check(const lr_matrix* Xm, int k, int p, double eps, const lr_options* opt) {
+  if (!Xm || !Xm->values) return fail(LR_EINVAL, "null matrix");
+  if (Xm->layout != LR_DENSE_COLMAJOR) return fail(LR_EINVAL, "only dense column-major X");
+  if (Xm->dtype < LR_F64 || Xm->dtype > LR_BF16) return fail(LR_EINVAL, "bad dtype");
+  const int64_t d = Xm->d, n = Xm->n;
+  if (d < 2 || n < 1 || Xm->ld < d) return fail(LR_EINVAL, "bad sizes");
+  if (!(1 <= k && k < p && p < d) || p > n || p > LR_MAX_P)
+    return fail(LR_EINVAL, "need 1 <= k < p < d, p <= n, p <= 64");
+  if (d > 0x7fffffff || n > 0x7fffffff) return fail(LR_EINVAL, "d and n must fit in int32");
+  if (!(eps > 0)) return fail(LR_EINVAL, "eps must be positive");
+  if (opt) {
+    if (opt->batch < 0 || opt->batch > 8192) return fail(LR_EINVAL, "batch must be in [0, 8192]");
+    if (opt->replay) {
+      const lr_schedule* r = opt->replay;
+      if (r->outer < 0 || (r->outer > 0 && !r->epochs) || r->b < 1 || r->b > n || r->b > 8192 ||
+          r->m < 1 || !(r->lambda > 0) || !(r->eta > 0))
+        return fail(LR_EINVAL, "bad replay schedule");
+    }
+  }
+  return LR_OK;
+}
+
+namespace {
+// Fill the size fields of a plan for X, k, p (no allocation).
+void plan_shape(lr_plan_s* pl, const lr_matrix* Xm, int k, int p) {
+  pl->X = lr::XView{Xm->values, Xm->d, Xm->n, Xm->ld, Xm->dtype};
+  pl->k = k;
+  pl->p = p;
+  pl->d = Xm->d;
+  pl->n = Xm->n;
+  pl->bmax = std::min<int64_t>(Xm->n, 8192);
+  pl->PC = lr::pad16(p);
+  pl->pb.nsplit = lr::pass_nsplit(Xm->d, Xm->n);
+}
+}  // namespace
+
+lr_status plan_bytes(const lr_matrix* Xm, int k, int p, const lr_options* opt, size_t* bytes) {
+  LR_CHECK(plan_check(Xm, k, p, 1.0, opt));
+  lr_plan_s tmp;
+  tmp.owns_ws = false;
+  tmp.owns_host = false;
+  plan_shape(&tmp, Xm, k, p);
+  *bytes = tmp.carve(nullptr);
+  return LR_OK;
+}
+
+lr_status plan_make(lr_plan_s** out, const lr_matrix* Xm, int k, int p, double eps,
+                    const lr_options* opt, hipStream_t st, void* ws, size_t ws_bytes,
+                    const HostRes* host) {
+  *out = nullptr;
+  LR_CHECK(plan_check(Xm, k, p, eps, opt));
+  lr_plan_s* pl = nullptr;
+  try {
+    pl = new lr_plan_s();
+  } catch (...) {
+    return fail(LR_ENOMEM, "host allocation failed");
+  }
+  pl->st = st;
+  pl->eps = eps;
+  if (opt)
+    pl->opt = *opt;
+  else
+    lowrank_options_default(&pl->opt);
+  plan_shape(pl, Xm, k, p);
+  if (pl->opt.replay) {
+    const lr_schedule* r = pl->opt.replay;
+    pl->replay = true;
+    pl->rsched = *r;
+    pl->repochs.assign(r->epochs, r->epochs + r->outer);
+    pl->rsched.epochs = nullptr;
+    pl->opt.replay = nullptr;
+  }
+  const size_t need = pl->carve(nullptr);
+  lr_status s = LR_OK;
+  if (ws) {
+    pl->owns_ws = false;
+    if (ws_bytes < need) s = fail(LR_EINVAL, "workspace smaller than the plan needs");
+    else pl->ws = ws;
+  } else if (hipMalloc(&pl->ws, need) != hipSuccess) {
+    (void)hipGetLastError();
+    pl->ws = nullptr;
+    s = fail(LR_ENOMEM, "device allocation failed");
+  }
+  if (s == LR_OK) pl->carve((char*)pl->ws);
+  if (s == LR_OK && host) {
+    pl->owns_host = false;
+    pl->hpin = host->hpin;
+    for (int i = 0; i < 8; ++i) pl->ev[i] = host->ev[i];
+  } else if (s == LR_OK) {
+    s = host_res_create(&pl->hpin, pl->ev);
+  }
+  if (s != LR_OK) {
+    delete pl;
+    return s;
+  }
+  *out = pl;
+  return LR_OK;
+}
+
+lr_status host_res_create(double** hpin, hipEvent_t* ev) {
+  if (hipHostMalloc((void**)hpin, HOST_PIN_BYTES) != hipSuccess) {
+    (void)hipGetLastError();
+    *hpin = nullptr;
+    return fail(LR_ENOMEM, "pinned host allocation failed");
+  }
+  for (int i = 0; i < 8; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) return fail(LR_EDEVICE, "hipEventCreate failed");
+  return LR_OK;
+}
+
+void host_res_destroy(double* hpin, hipEvent_t* ev) {
+  if (hpin) (void)hipHostFree(hpin);
+  for (int i = 0; i < 8; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+}
+
+}  // namespace lr
+
 extern "C" {
 
 const char* lowrank_status_string(lr_status s) {
@@ -444,108 +600,14 @@ lr_status lowrank_plan(lr_plan* out, const lr_matrix* Xm, int k, int p, double e
                        const lr_options* opt, void* hip_stream) {
   if (!out) return fail(LR_EINVAL, "null plan pointer");
   *out = nullptr;
-  if (!Xm || !Xm->values) return fail(LR_EINVAL, "null matrix");
-  if (Xm->layout != LR_DENSE_COLMAJOR) return fail(LR_EINVAL, "only dense column-major X");
-  if (Xm->dtype < LR_F64 || Xm->dtype > LR_BF16) return fail(LR_EINVAL, "bad dtype");
-  const int64_t d = Xm->d, n = Xm->n;
-  if (d < 2 || n < 1 || Xm->ld < d) return fail(LR_EINVAL, "bad sizes");
-  if (!(1 <= k && k < p && p < d) || p > n || p > LR_MAX_P)
-    return fail(LR_EINVAL, "need 1 <= k < p < d, p <= n, p <= 64");
-  if (d > 0x7fffffff || n > 0x7fffffff) return fail(LR_EINVAL, "d and n must fit in int32");
-  if (!(eps > 0)) return fail(LR_EINVAL, "eps must be positive");
-  lr_plan_s* pl = nullptr;
-  try {
-    pl = new lr_plan_s();
-  } catch (...) {
-    return fail(LR_ENOMEM, "host allocation failed");
-  }
-  pl->st = (hipStream_t)hip_stream;
-  pl->X = lr::XView{Xm->values, d, n, Xm->ld, Xm->dtype};
-  pl->k = k;
-  pl->p = p;
-  pl->eps = eps;
-  if (opt)
-    pl->opt = *opt;
-  else
-    lowrank_options_default(&pl->opt);
-  pl->d = d;
-  pl->n = n;
-  if (pl->opt.batch < 0 || pl->opt.batch > 8192) {
-    delete pl;
-    return fail(LR_EINVAL, "batch must be in [0, 8192]");
-  }
-  int64_t bmax = std::min<int64_t>(n, 8192);
-  if (pl->opt.replay) {
-    const lr_schedule* r = pl->opt.replay;
-    if (r->outer < 0 || (r->outer > 0 && !r->epochs) || r->b < 1 || r->b > n || r->b > 8192 ||
-        r->m < 1 ||
-        !(r->lambda > 0) || !(r->eta > 0)) {
-      delete pl;
-      return fail(LR_EINVAL, "bad replay schedule");
-    }
-    pl->replay = true;
-    pl->rsched = *r;
-    pl->repochs.assign(r->epochs, r->epochs + r->outer);
-    pl->rsched.epochs = nullptr;
-    pl->opt.replay = nullptr;
-  }
-  pl->bmax = bmax;
-  pl->PC = lr::pad16(p);
-  const int64_t dp = d * p;
-  lr_status s = LR_OK;
-  const int64_t nbt = (n + 1023) / 1024;
-  const size_t partn = std::max<size_t>((size_t)lr::gram_nblk(std::max(d, n)) * 64 * 64, 1024);
-#define A_(ptr, cnt)                 \
-  if (s == LR_OK) s = pl->alloc(&pl->ptr, (size_t)(cnt));
-  A_(w, n);
-  A_(cdf, n + 1);
-  A_(scratch, 3 * nbt + 8);
-  A_(S, dp);
-  A_(W, dp);
-  A_(Wt, dp);
-  A_(G, dp);
-  A_(Y, dp);
-  A_(Dl, dp);
-  A_(Tm1, dp);
-  A_(Tm2, dp);
-  A_(Sest, dp);
-  A_(V, d * k);
-  A_(Vprev, d * k);
-  A_(T, n * lr::pad16(p));
-  const int nsplit = lr::pass_nsplit(d, n);
-  pl->pb.nsplit = nsplit;
-  A_(Ypart, (int64_t)nsplit * dp);
-  A_(C, bmax * lr::pad16(p));
-  A_(scale, lr_plan_s::MCH * bmax);
-  A_(idx, lr_plan_s::MCH * bmax);
-  A_(part, partn);
-  A_(H, 64 * 64);
-  A_(Q, 64 * 64);
-  A_(vals, 64);
-  A_(M, 64 * 64);
-  A_(Rinv, 64 * 64);
-  A_(kk1, 64 * 64);
-  A_(kk2, 64 * 64);
-  A_(res, 64);
-  A_(dfro2, 1);
-  A_(dnorm, 4);
-  A_(dinfo, 1);
-  A_(dbad, 1);
-#undef A_
-  if (s == LR_OK && hipHostMalloc((void**)&pl->hpin, 64 * 64 * sizeof(double) * 2) != hipSuccess) {
-    (void)hipGetLastError();
-    pl->hpin = nullptr;
-    s = fail(LR_ENOMEM, "pinned host allocation failed");
-  }
-  for (int i = 0; s == LR_OK && i < 8; ++i)
-    if (hipEventCreate(&pl->ev[i]) != hipSuccess) s = fail(LR_EDEVICE, "hipEventCreate failed");
-  if (s != LR_OK) {
-    delete pl;
-    return s;
-  }
-  pl->pb.Ypart = pl->Ypart;
-  *out = pl;
-  return LR_OK;
+  return lr::plan_make(out, Xm, k, p, eps, opt, (hipStream_t)hip_stream, nullptr, 0, nullptr);
+}
+
+lr_status lowrank_plan_bytes(const lr_matrix* X, int k, int p, const lr_options* opt,
+                             size_t* bytes) {
+  if (!bytes) return fail(LR_EINVAL, "null output");
+  *bytes = 0;
+  return lr::plan_bytes(X, k, p, opt, bytes);
 }
 
 lr_status lowrank_solve(lr_plan plan, double* U_out, double* theta_out, lr_report* rep) {

@@ -17,6 +17,7 @@ LR_OK, LR_EINVAL, LR_ENOMEM, LR_ENOGAP, LR_ENOCONV, LR_ESHIFT, LR_ENOTSPD, LR_ED
     range(9)
 LR_MAX_P = 64
 LR_MAX_SHIFT_ROUNDS = 64
+LR_MAX_SLOTS = 16
 LR_F64, LR_F32, LR_BF16 = 0, 1, 2
 
 
@@ -58,6 +59,20 @@ class lr_report(ctypes.Structure):
                 ("ms_update_probe", ctypes.c_double), ("probes", ctypes.c_int64)]
 
 
+class lr_ticket_info(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("slot", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_uint64)]
+
+
+class lr_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("budget_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
+                ("peak_bytes", ctypes.c_uint64), ("slots", ctypes.c_int32),
+                ("peak_running", ctypes.c_int32), ("elapsed", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); the full exported surface of include/lowrank.h
 _P = ctypes.c_void_p
 SIGNATURES = {
@@ -70,6 +85,9 @@ SIGNATURES = {
                                      ctypes.POINTER(lr_report)]),
     "lowrank_get_schedule": (ctypes.c_int, [_P, ctypes.POINTER(lr_schedule)]),
     "lowrank_destroy": (None, [_P]),
+    "lowrank_plan_bytes": (ctypes.c_int, [ctypes.POINTER(lr_matrix), ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(lr_options),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
     "lowrank_op_apply_A": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "lowrank_op_prepare": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "lowrank_op_sample": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -80,6 +98,17 @@ SIGNATURES = {
     "lowrank_op_svrg_solve": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                              ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
+    "lowrank_server_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.c_int]),
+    "lowrank_submit": (ctypes.c_int, [_P, ctypes.POINTER(lr_matrix), ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_double, ctypes.POINTER(lr_options), _P,
+                                      ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_uint64)]),
+    "lowrank_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(lr_report),
+                                    ctypes.POINTER(lr_ticket_info)]),
+    "lowrank_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(lr_report),
+                                    ctypes.POINTER(lr_ticket_info)]),
+    "lowrank_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(lr_server_stats)]),
+    "lowrank_server_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -154,6 +183,43 @@ class Schedule:
         return s, arr
 
 
+def _matrix(Xt):
+    if not Xt.is_cuda or Xt.dim() != 2 or not Xt.is_contiguous():
+        raise ValueError("X must be a contiguous 2-D device tensor of shape (n, d)")
+    n, d = Xt.shape
+    return lr_matrix(d=d, n=n, ld=d, nnz=0, dtype=_dtype_code(Xt), layout=0,
+                     values=Xt.data_ptr(), col_ptr=None, row_idx=None)
+
+
+def make_options(seed=0, shift_mode=0, est_iters=4, max_outer=2000, max_epochs=60,
+                 max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0, tau_shift=1e-2,
+                 replay=None, timing=0):
+    """lr_options plus the host objects it points to (kept alive by the caller)."""
+    lib = load_library()
+    opt = lr_options()
+    lib.lowrank_options_default(ctypes.byref(opt))
+    opt.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    opt.shift_mode, opt.est_iters, opt.max_outer = shift_mode, est_iters, max_outer
+    opt.max_epochs, opt.max_shift_rounds, opt.polish = max_epochs, max_shift_rounds, polish
+    opt.batch, opt.eta_scale, opt.tau_shift, opt.timing = batch, eta_scale, tau_shift, timing
+    keep = None
+    if replay is not None:
+        sc, arr = replay.to_c()
+        keep = (sc, arr)
+        opt.replay = ctypes.pointer(sc)
+    return opt, keep
+
+
+def plan_bytes(Xt, k, p, **kw):
+    """Device workspace bytes of a plan (or server request) for this problem."""
+    lib = load_library()
+    mat = _matrix(Xt)
+    opt, _keep = make_options(**kw)
+    out = ctypes.c_size_t()
+    _check(lib.lowrank_plan_bytes(ctypes.byref(mat), k, p, ctypes.byref(opt), ctypes.byref(out)))
+    return out.value
+
+
 class Plan:
     """A plan over a device matrix X given as an (n, d) C-contiguous tensor, i.e.
     X (d x n) in column-major order; each row of the tensor is a data point."""
@@ -163,25 +229,15 @@ class Plan:
                  tau_shift=1e-2, replay=None, timing=0):
         import torch
         self.lib = load_library()
-        if not Xt.is_cuda or Xt.dim() != 2 or not Xt.is_contiguous():
-            raise ValueError("X must be a contiguous 2-D device tensor of shape (n, d)")
+        self._mat = _matrix(Xt)
         self.Xt = Xt
         n, d = Xt.shape
         self.d, self.n, self.k, self.p = d, n, k, p
         self.device = Xt.device
-        self._mat = lr_matrix(d=d, n=n, ld=d, nnz=0, dtype=_dtype_code(Xt), layout=0,
-                              values=Xt.data_ptr(), col_ptr=None, row_idx=None)
-        opt = lr_options()
-        self.lib.lowrank_options_default(ctypes.byref(opt))
-        opt.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
-        opt.shift_mode, opt.est_iters, opt.max_outer = shift_mode, est_iters, max_outer
-        opt.max_epochs, opt.max_shift_rounds, opt.polish = max_epochs, max_shift_rounds, polish
-        opt.batch, opt.eta_scale, opt.tau_shift, opt.timing = batch, eta_scale, tau_shift, timing
-        self._replay_keep = None
-        if replay is not None:
-            sc, arr = replay.to_c()
-            self._replay_keep = (sc, arr)
-            opt.replay = ctypes.pointer(sc)
+        opt, self._replay_keep = make_options(
+            seed=seed, shift_mode=shift_mode, est_iters=est_iters, max_outer=max_outer,
+            max_epochs=max_epochs, max_shift_rounds=max_shift_rounds, polish=polish, batch=batch,
+            eta_scale=eta_scale, tau_shift=tau_shift, replay=replay, timing=timing)
         self._opt = opt
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -274,6 +330,86 @@ class Plan:
         _check(self.lib.lowrank_op_svrg_solve(self._h, _ptr(Sc), float(lam), float(eta), int(m),
                                               int(b), int(solve), int(epochs), _ptr(W), res))
         return W.T, np.array(res[:])
+
+
+class Server:
+    """Request server over the library's continuous-batching loop.
+
+    submit() queues one problem (X as for Plan) and returns a ticket; wait() or
+    poll() hand back (status, U d x k, theta, report, info) once it finished.
+    The binding keeps X and the output buffers of every pending request alive.
+    """
+
+    def __init__(self, budget_bytes, slots=4, device=None):
+        import torch
+        self.lib = load_library()
+        self.device = torch.device(device) if device is not None else \
+            torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.lowrank_server_create(ctypes.byref(h), int(budget_bytes), int(slots)))
+        self._h = h
+        self._pending = {}
+
+    def submit(self, Xt, k, p, eps, sync=True, **kw):
+        import torch
+        mat = _matrix(Xt)
+        opt, keep = make_options(**kw)
+        d = Xt.shape[1]
+        U = torch.empty((k, d), dtype=torch.float64, device=Xt.device)
+        theta = (ctypes.c_double * k)()
+        if sync:   # the server's streams do not wait on torch's
+            torch.cuda.current_stream(Xt.device).synchronize()
+        t = ctypes.c_uint64()
+        _check(self.lib.lowrank_submit(self._h, ctypes.byref(mat), k, p, float(eps),
+                                       ctypes.byref(opt), _ptr(U), theta, ctypes.byref(t)))
+        self._pending[t.value] = (Xt, U, theta, keep, k, p)
+        return t.value
+
+    def _finish(self, ticket, st, rep, info):
+        Xt, U, theta, _keep, k, p = self._pending.pop(ticket)
+        inf = {"t_submit": info.t_submit, "t_admit": info.t_admit, "t_done": info.t_done,
+               "slot": info.slot, "workspace_bytes": info.workspace_bytes}
+        return st, U.T, np.array(theta[:]), report_dict(rep, p), inf
+
+    def poll(self, ticket):
+        """None while pending, else (status, U, theta, report, info)."""
+        rep, info = lr_report(), lr_ticket_info()
+        st = self.lib.lowrank_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(rep),
+                                   ctypes.byref(info))
+        if st == LR_EBUSY:
+            return None
+        if st == LR_EINVAL and ticket not in self._pending:
+            _check(st)
+        return self._finish(ticket, st, rep, info)
+
+    def wait(self, ticket):
+        rep, info = lr_report(), lr_ticket_info()
+        st = self.lib.lowrank_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(rep),
+                                   ctypes.byref(info))
+        if st == LR_EINVAL and ticket not in self._pending:
+            _check(st)
+        return self._finish(ticket, st, rep, info)
+
+    def error(self):
+        return self.lib.lowrank_last_error().decode()
+
+    def stats(self):
+        s = lr_server_stats()
+        _check(self.lib.lowrank_server_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in lr_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.lowrank_server_destroy(self._h)
+            self._h = None
+            self._pending.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def report_dict(rep, p):

@@ -1,0 +1,76 @@
+"""Host-side logic of the library that needs no GPU: the server's HBM arena
+(first-fit allocator, checked against a brute-force occupancy map), workspace
+sizing and the server's argument checks."""
+import ctypes
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1607_02925_amd", "csrc")
+
+
+def test_arena_first_fit_against_brute_force(tmp_path):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    exe = str(tmp_path / "arena_check")
+    subprocess.run([gxx, "-O1", "-std=c++17", "-Wall", "-Werror", "-I", CSRC,
+                    os.path.join(ROOT, "tests", "arena_check.cpp"), "-o", exe], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "arena ok" in r.stdout
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1607_02925_amd import lowrank, build
+    if not os.path.exists(lowrank.LIB_PATH):
+        build.build()
+    return lowrank.load_library()
+
+
+def _mat(d, n, dtype=1):
+    from paper_1607_02925_amd import lowrank
+    return lowrank.lr_matrix(d=d, n=n, ld=d, nnz=0, dtype=dtype, layout=0, values=1,
+                             col_ptr=None, row_idx=None)
+
+
+def test_plan_bytes(lib):
+    """Workspace is dominated by X^T W (n x pad16(p) FP64), the sampling table
+    (16 bytes per column) and the minibatch staging; it grows with n and p."""
+    from paper_1607_02925_amd import lowrank
+    out = ctypes.c_size_t()
+    m = _mat(2048, 200000)
+    assert lib.lowrank_plan_bytes(ctypes.byref(m), 10, 20, None, ctypes.byref(out)) == 0
+    b = out.value
+    assert b % 256 == 0
+    assert b >= 200000 * 32 * 8 + 200000 * 16
+    assert b < 200000 * 32 * 8 + 200000 * 16 + 2 ** 28
+    m2 = _mat(2048, 400000)
+    assert lib.lowrank_plan_bytes(ctypes.byref(m2), 10, 20, None, ctypes.byref(out)) == 0
+    assert out.value > b
+    assert lib.lowrank_plan_bytes(ctypes.byref(m), 10, 40, None, ctypes.byref(out)) == 0
+    assert out.value > b
+    assert lib.lowrank_plan_bytes(ctypes.byref(m), 20, 20, None, ctypes.byref(out)) == \
+        lowrank.LR_EINVAL
+
+
+def test_server_argument_checks_without_gpu(lib):
+    """Checks that happen before any device call."""
+    from paper_1607_02925_amd import lowrank
+    h = ctypes.c_void_p()
+    assert lib.lowrank_server_create(ctypes.byref(h), 1 << 30, 0) == lowrank.LR_EINVAL
+    assert lib.lowrank_server_create(ctypes.byref(h), 1 << 30, lowrank.LR_MAX_SLOTS + 1) == \
+        lowrank.LR_EINVAL
+    assert lib.lowrank_server_create(ctypes.byref(h), 16, 1) == lowrank.LR_EINVAL
+    assert lib.lowrank_server_create(None, 1 << 30, 1) == lowrank.LR_EINVAL
+    t = ctypes.c_uint64()
+    m = _mat(100, 50)
+    assert lib.lowrank_submit(None, ctypes.byref(m), 2, 4, 1e-4, None, None, None,
+                              ctypes.byref(t)) == lowrank.LR_EINVAL
+    assert lib.lowrank_poll(None, 1, None, None) == lowrank.LR_EINVAL
+    assert lib.lowrank_wait(None, 1, None, None) == lowrank.LR_EINVAL
+    lib.lowrank_server_destroy(None)

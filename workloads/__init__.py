@@ -9,3 +9,4 @@ from .planted import (  # noqa: F401
     SPECTRA, spectrum, haar_orthogonal, planted_dense, planted_dense_torch,
     f64_to_bf16_bits, workload, WORKLOADS,
 )
+from . import serving  # noqa: F401

@@ -100,18 +100,27 @@ def planted_dense(d, n, sigma, seed, storage="f64", noise_std=0.0):
 
 
 def planted_dense_torch(d, n, sigma, seed, storage="f32", noise_std=0.0,
-                        device="cuda", chunk=65536):
+                        device="cuda", chunk=65536, u_on_device=False):
     """Large-size generator: U from NumPy (seeded), V and noise from a seeded
     torch generator on ``device``.  Returns dict with Xt as a device tensor of
     the storage dtype (torch.float64 / float32 / bfloat16), plus U and sigma.
-    X is formed as Xt = G (R^{-1} diag(sigma) U^T), with G^T G = R^T R."""
+    X is formed as Xt = G (R^{-1} diag(sigma) U^T), with G^T G = R^T R.
+    With ``u_on_device`` U is drawn by the same torch generator (QR of a
+    Gaussian on the device, diagonal of R made positive) instead of NumPy,
+    which avoids a host QR per matrix when many are generated."""
     import torch
     sigma = np.asarray(sigma, dtype=np.float64)
     assert n >= d and sigma.shape == (d,)
-    rng = np.random.default_rng(seed)
-    u = haar_orthogonal(d, rng)
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
+    if u_on_device:
+        gq = torch.randn((d, d), generator=gen, dtype=torch.float64, device=device)
+        q, r = torch.linalg.qr(gq)
+        u_dev = q * torch.sign(torch.diagonal(r))[None, :]
+        u = u_dev.cpu().numpy()
+    else:
+        rng = np.random.default_rng(seed)
+        u = haar_orthogonal(d, rng)
     g = torch.randn((n, d), generator=gen, dtype=torch.float64, device=device)
     gram = torch.zeros((d, d), dtype=torch.float64, device=device)
     for c0 in range(0, n, chunk):
