@@ -15,4 +15,5 @@ from .linalg import cholqr, cholqr2, eigh_desc, jacobi_svd, sin_theta, sign_fix 
 from .lowrank import (  # noqa: F401
     Options, Schedule, Result, LowRankError, solve, decode, apply_A, estimate_phase,
     solver_constants, svrg_step, svrg_solve, tune_shift, si_iterate, final_rr,
+    LR_OK, LR_EINVAL, LR_ENOMEM, LR_ENOGAP, LR_ENOCONV, LR_ESHIFT, LR_ENOTSPD,
 )

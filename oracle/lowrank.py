@@ -81,7 +81,26 @@ class Schedule:
 
 
 def decode(xt, storage):
-    """X (d x n, float64) from the stored column-major array xt (n x d)."""
+    """X (d x n, float64) from its stored form.
+
+    Dense storage ("f64", "f32", "bf16"): xt is the column-major array (n x d).
+    Compressed-column storage ("csc-f64", "csc-f32", "csc-bf16"): xt is a dict
+    with d, n, col_ptr, row_idx, values; X becomes a scipy.sparse CSC matrix
+    whose stored values are upcast exactly.  The paper allows sparse X with the
+    per-pass cost nnz(X) in place of dn (Section 1 footnote; Theorem
+    "svrgSolve").  Row indices must be sorted within each column, so that the
+    stored order of a column is its row order."""
+    if storage.startswith("csc-"):
+        import scipy.sparse as sps
+        vals = np.asarray(xt["values"])
+        if storage == "csc-bf16":
+            vals = (vals.astype(np.uint32) << np.uint32(16)).view(np.float32)
+        cp = np.asarray(xt["col_ptr"], dtype=np.int64)
+        ri = np.asarray(xt["row_idx"], dtype=np.int64)
+        X = sps.csc_matrix((vals.astype(np.float64), ri, cp), shape=(xt["d"], xt["n"]))
+        if not X.has_sorted_indices:
+            raise LowRankError(LR_EINVAL, "row indices must be sorted within each column")
+        return X
     if storage == "bf16":
         bits = np.asarray(xt, dtype=np.uint16).astype(np.uint32) << np.uint32(16)
         return bits.view(np.float32).astype(np.float64).T

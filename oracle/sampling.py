@@ -28,9 +28,19 @@ QBITS = 24
 
 def column_sq_norms(X):
     """w_i = ||x_i||^2 for the columns of X (d x n, float64), accumulated in
-    row order so that every implementation performs the same roundings."""
+    row order so that every implementation performs the same roundings.  For a
+    CSC matrix with sorted row indices the stored entries of a column are
+    visited in that same row order (the skipped zeros would add exactly 0)."""
     d, n = X.shape
     w = np.zeros(n, dtype=np.float64)
+    if hasattr(X, "indptr"):
+        ptr = X.indptr.astype(np.int64)
+        length = np.diff(ptr)
+        for t in range(int(length.max()) if n else 0):
+            has = length > t
+            v = X.data[ptr[:-1][has] + t]
+            w[has] += v * v
+        return w
     for j in range(d):
         row = X[j, :]
         w += row * row

@@ -10,3 +10,4 @@ from .planted import (  # noqa: F401
     f64_to_bf16_bits, workload, WORKLOADS,
 )
 from . import serving  # noqa: F401
+from . import sparse  # noqa: F401

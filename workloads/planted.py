@@ -163,13 +163,29 @@ WORKLOADS = {
     "planted-512x16384-bf16": dict(d=512, n=16384, spectrum="powerlaw", storage="bf16",
                                    noise_std=0.0, k=32, p=48, eps=1e-4, data_seed=2004,
                                    solver_seed=0x1607029250000014),
+    # compressed-column sparse X with Zipf(1.1) rows (workloads/sparse.py)
+    "zipf-50000x1000000-csc-f32": dict(d=50000, n=1000000, nnz_col=32, storage="csc-f32",
+                                       k=16, p=32, eps=1e-3, data_seed=1003,
+                                       solver_seed=0x1607029250000003),
+    "zipf-2000x20000-csc-f32": dict(d=2000, n=20000, nnz_col=32, storage="csc-f32",
+                                    k=16, p=32, eps=1e-3, data_seed=2003,
+                                    solver_seed=0x1607029250000013),
 }
 
 
 def workload(name, device=None):
     """Build a named workload.  With ``device`` (e.g. "cuda") the large-size
-    torch generator is used and Xt is a device tensor; otherwise NumPy."""
+    torch generator is used and Xt is a device tensor; otherwise NumPy.  For
+    compressed-column workloads Xt is the CSC dict of workloads.sparse (NumPy,
+    whatever ``device`` says)."""
     w = dict(WORKLOADS[name])
+    if w["storage"].startswith("csc-"):
+        from .sparse import zipf_csc
+        sp = zipf_csc(w["d"], w["n"], w["nnz_col"], seed=w["data_seed"], storage=w["storage"])
+        w.update(sp)
+        w["Xt"] = sp
+        w["name"] = name
+        return w
     sig = spectrum(w["spectrum"], min(w["d"], w["n"]))
     if device is None:
         data = planted_dense(w["d"], w["n"], sig, w["data_seed"], w["storage"], w["noise_std"])
