@@ -67,9 +67,17 @@ typedef enum {
 typedef enum { LR_F64 = 0, LR_F32 = 1, LR_BF16 = 2 } lr_dtype;
 typedef enum { LR_DENSE_COLMAJOR = 0, LR_CSC = 1 } lr_layout;
 
-/* The input matrix.  values: device pointer to d x n elements of `dtype`
- * (BF16 as raw uint16 bit patterns).  Only LR_DENSE_COLMAJOR is implemented;
- * col_ptr, row_idx and nnz are reserved for the compressed-column layout. */
+/* The input matrix, all pointers on the device; values of `dtype` (BF16 as raw
+ * uint16 bit patterns).
+ *   LR_DENSE_COLMAJOR: values holds d x n elements, (r, i) at values[i*ld + r];
+ *     nnz, col_ptr and row_idx are ignored.
+ *   LR_CSC (compressed columns, i.e. CSR of X^T; the paper allows sparse X with
+ *     per-pass cost nnz(X), Section 1 footnote and Theorem "svrgSolve"): column
+ *     i's entries are [col_ptr[i], col_ptr[i+1]) of row_idx / values; col_ptr
+ *     has n + 1 entries rising from 0 to nnz (< 2^31); row ids lie in [0, d) and
+ *     increase within each column.  lowrank_plan checks this structure on the
+ *     device (LR_EINVAL otherwise) and builds a row-ordered copy of X that the
+ *     plan owns; ld is ignored.  The request server takes dense X only. */
 typedef struct lr_matrix {
   int64_t d, n, ld, nnz;
   int32_t dtype;          /* lr_dtype */
@@ -173,9 +181,12 @@ lr_status lowrank_get_schedule(lr_plan plan, lr_schedule* out);
 
 void lowrank_destroy(lr_plan plan);
 
-/* Device workspace in bytes that lowrank_plan (or a server) allocates for
- * this problem: the n-length sampling table, the n x pad16(p) block X^T W, the
- * d x p iterates and the minibatch staging.  Same checks as lowrank_plan. */
+/* Device workspace in bytes that lowrank_plan (or a server) keeps for this
+ * problem: the n-length sampling table, the n x pad16(p) block X^T W, the d x p
+ * iterates and the minibatch staging; for LR_CSC also the row-ordered copy of
+ * X and its chunk tables (plan creation needs about 12 nnz + sort-scratch bytes
+ * more while it builds that copy).  Same checks as lowrank_plan, done on the
+ * host only. */
 lr_status lowrank_plan_bytes(const lr_matrix* X, int k, int p, const lr_options* opt,
                              size_t* bytes);
 

@@ -17,6 +17,7 @@
 
 #include "engine.h"
 #include "kernels.h"
+#include "sparse.h"
 
 namespace {
 
@@ -54,6 +55,16 @@ std::string last_error() { return g_err; }
 struct lr_plan_s {
   hipStream_t st = nullptr;
   lr::XView X{};
+  // compressed-column X: the caller's CSC view, the row-ordered copy built at
+  // plan time (owned, separate allocations) and the row-major d x PC blocks
+  bool sparse = false;
+  lr::CscView Xs{};
+  lr::CsrView R{};
+  std::vector<void*> sp_allocs;
+  int32_t *sp_head_slot = nullptr, *sp_head_row = nullptr;
+  int sp_H = 0;
+  double* sp_part = nullptr;
+  double *Wrm = nullptr, *Grm = nullptr, *Dlrm = nullptr;
   int k = 0, p = 0;
   double eps = 0;
   lr_options opt{};
@@ -87,6 +98,7 @@ struct lr_plan_s {
   lr_report rep{};
 
   ~lr_plan_s() {
+    for (void* a : sp_allocs) (void)hipFree(a);
     if (owns_ws && ws) (void)hipFree(ws);
     if (owns_host) {
       if (hpin) (void)hipHostFree(hpin);
@@ -114,15 +126,31 @@ struct lr_plan_s {
     return LR_OK;
   }
 
+  // T = X^T W (n x PC row-major)   (W: d x ncols)
+  lr_status xtw(const double* Win, int ncols) {
+    if (sparse) {
+      LR_HIP(lr::cm_to_rm(Win, d, ncols, Wrm, PC, st));
+      LR_HIP(lr::csc_xtw(Xs, Wrm, PC, T, st));
+    } else {
+      LR_HIP(lr::pass_xtw(X, Win, ncols, T, PC, st));
+    }
+    return LR_OK;
+  }
+
   // Y = alpha X (X^T W) + beta A + gamma B   (W: d x ncols)
   lr_status applyA(const double* Win, double* Yout, int ncols, double alpha = 1.0,
                    const double* A = nullptr, double beta = 0.0, const double* B = nullptr,
                    double gamma = 0.0) {
-    LR_HIP(lr::pass_xtw(X, Win, ncols, T, PC, st));
-    LR_HIP(lr::pass_xt(X, T, PC, ncols, pb, alpha, A, beta, B, gamma, Yout, st));
+    LR_CHECK(xtw(Win, ncols));
+    if (sparse)
+      LR_HIP(lr::csr_xt(R, T, PC, ncols, sp_part, alpha, A, beta, B, gamma, Yout, st));
+    else
+      LR_HIP(lr::pass_xt(X, T, PC, ncols, pb, alpha, A, beta, B, gamma, Yout, st));
     rep.passes++;
     return LR_OK;
   }
+
+  lr_status sparse_setup();
 
   lr_status gram_dd(const double* A, int pa, const double* B, int pb_, double* out) {
     LR_HIP(lr::gram(A, 1, d, pa, B, 1, d, pb_, d, part, out, st));
@@ -142,7 +170,10 @@ struct lr_plan_s {
 
   lr_status prepare() {
     LR_HIP(hipMemsetAsync(dbad, 0, sizeof(int), st));
-    LR_HIP(lr::colnorms(X, w, dbad, st));
+    if (sparse)
+      LR_HIP(lr::csc_colnorms(Xs, w, dbad, st));
+    else
+      LR_HIP(lr::colnorms(X, w, dbad, st));
     int bad = 0;
     LR_CHECK(read(&bad, dbad, sizeof(int)));
     if (bad) return fail(LR_EINVAL, "non-finite entries in X");
@@ -201,7 +232,12 @@ struct lr_plan_s {
       } else if (e >= fixed_epochs) {
         break;
       }
-      LR_HIP(hipMemsetAsync(Dl, 0, cnt * sizeof(double), st));
+      if (sparse) {
+        LR_HIP(lr::cm_to_rm(G, d, p, Grm, PC, st));
+        LR_HIP(hipMemsetAsync(Dlrm, 0, d * PC * sizeof(double), st));
+      } else {
+        LR_HIP(hipMemsetAsync(Dl, 0, cnt * sizeof(double), st));
+      }
       if (opt.timing) LR_HIP(hipEventRecord(ev[0], st));
       const int64_t tprobe = m / 2;  // one launch per epoch is timed per kernel
       for (int64_t t0 = 0; t0 < m; t0 += MCH) {
@@ -218,10 +254,18 @@ struct lr_plan_s {
             pu.start = ev[6];
             pu.stop = ev[7];
           }
-          LR_HIP(lr::step_dot(X, p, b, it, scale + (t - t0) * b, Dl, C, PC, st, pd));
-          LR_HIP(lr::step_update(X, p, b, it, C, PC, G, Dl, lam, eta, st, pu));
+          if (sparse) {
+            LR_HIP(lr::csc_step_dot(Xs, b, it, scale + (t - t0) * b, Dlrm, C, PC, st, pd));
+            LR_HIP(lr::rm_decay(d * PC, Grm, Dlrm, lam, eta, st));
+            LR_HIP(lr::csc_step_scatter(Xs, b, it, C, PC, p, sp_head_slot, sp_head_row, sp_H,
+                                        eta, Dlrm, st, pu));
+          } else {
+            LR_HIP(lr::step_dot(X, p, b, it, scale + (t - t0) * b, Dl, C, PC, st, pd));
+            LR_HIP(lr::step_update(X, p, b, it, C, PC, G, Dl, lam, eta, st, pu));
+          }
         }
       }
+      if (sparse) LR_HIP(lr::rm_to_cm(Dlrm, d, p, PC, Dl, st));
       if (opt.timing) LR_HIP(hipEventRecord(ev[1], st));
       rep.steps += m;
       LR_HIP(lr::lincomb(cnt, 1.0, Wt, 1.0, Dl, 0.0, nullptr, Wt, st));
@@ -391,7 +435,7 @@ lr_status lr_plan_s::solve(double* U_out, double* theta_out, lr_report* out_rep)
     LR_CHECK(applyA(S, Y, p));
     LR_CHECK(cholqr2(Y, S, p));
   }
-  LR_HIP(lr::pass_xtw(X, S, p, T, PC, st));
+  LR_CHECK(xtw(S, p));
   LR_HIP(lr::gram(T, PC, 1, p, T, PC, 1, p, n, part, H, st));
   LR_HIP(lr::eigh(H, p, vals, Q, st));
   double* Uo = U_out ? U_out : Tm2;
@@ -423,6 +467,7 @@ size_t lr_plan_s::carve(char* base) {
   for (double** b : {&S, &W, &Wt, &G, &Y, &Dl, &Tm1, &Tm2, &Sest}) take(b, dp);
   take(&V, d * k);
   take(&Vprev, d * k);
+  for (double** b : {&Wrm, &Grm, &Dlrm}) take(b, sparse ? d * PC : 0);
   take(&T, n * PC);
   take(&Ypart, (int64_t)pb.nsplit * dp);
   take(&C, bmax * PC);
@@ -440,14 +485,117 @@ size_t lr_plan_s::carve(char* base) {
   return (off + 255) & ~(size_t)255;
 }
 
+lr_status lr_plan_s::sparse_setup() {
+  const int64_t nnz = Xs.nnz;
+  const size_t elt = Xs.dt == LR_F64 ? 8 : Xs.dt == LR_F32 ? 4 : 2;
+  auto keep = [&](void** ptr, size_t bytes) -> lr_status {
+    if (hipMalloc(ptr, std::max<size_t>(bytes, 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      *ptr = nullptr;
+      return fail(LR_ENOMEM, "device allocation failed");
+    }
+    sp_allocs.push_back(*ptr);
+    return LR_OK;
+  };
+  // structure checks; row ids are read only once col_ptr is known to be sound
+  int bad = 0;
+  LR_HIP(hipMemsetAsync(dbad, 0, sizeof(int), st));
+  LR_HIP(lr::csc_check_ptr(Xs, dbad, st));
+  LR_CHECK(read(&bad, dbad, sizeof(int)));
+  if (bad) return fail(LR_EINVAL, "CSC col_ptr must rise from 0 to nnz");
+  LR_HIP(lr::csc_check_rows(Xs, dbad, st));
+  LR_CHECK(read(&bad, dbad, sizeof(int)));
+  if (bad) return fail(LR_EINVAL, "CSC row ids must lie in [0, d) and increase within each column");
+  // row-ordered copy: stable radix sort of the row ids keeps columns ascending
+  void *col = nullptr, *val = nullptr;
+  LR_CHECK(keep(&col, (size_t)nnz * 4));
+  LR_CHECK(keep(&val, (size_t)nnz * elt));
+  size_t tb = 0;
+  LR_HIP(lr::csr_sort_bytes(nnz, d, &tb));
+  void* tmp[5] = {};
+  const size_t tmp_bytes[5] = {tb, (size_t)nnz * 4, (size_t)nnz * 4, (size_t)nnz * 4,
+                               (size_t)(d + 1) * 4};
+  lr_status s = LR_OK;
+  for (int i = 0; i < 5 && s == LR_OK; ++i)
+    if (hipMalloc(&tmp[i], std::max<size_t>(tmp_bytes[i], 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      tmp[i] = nullptr;
+      s = fail(LR_ENOMEM, "device allocation failed");
+    }
+  std::vector<int32_t> row_ptr(d + 1);
+  if (s == LR_OK) {
+    hipError_t e = lr::csr_build(Xs, tmp[0], tb, (uint32_t*)tmp[1], (int32_t*)tmp[2],
+                                 (int32_t*)tmp[3], (int32_t*)tmp[4], (int32_t*)col, val, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(row_ptr.data(), tmp[4], (d + 1) * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) s = fail(LR_EDEVICE, std::string("CSR build: ") + hipGetErrorString(e));
+  }
+  (void)hipStreamSynchronize(st);
+  for (void* t : tmp)
+    if (t) (void)hipFree(t);
+  LR_CHECK(s);
+  // chunks of at most SP_CHUNK entries per row; rows without entries own none
+  std::vector<int32_t> row_chunk(d + 1), chunk_beg;
+  chunk_beg.reserve(d + nnz / lr::SP_CHUNK + 2);
+  for (int64_t r = 0; r < d; ++r) {
+    row_chunk[r] = (int32_t)chunk_beg.size();
+    for (int64_t b = row_ptr[r]; b < row_ptr[r + 1]; b += lr::SP_CHUNK) chunk_beg.push_back((int32_t)b);
+  }
+  row_chunk[d] = (int32_t)chunk_beg.size();
+  const int64_t nch = (int64_t)chunk_beg.size();
+  chunk_beg.push_back((int32_t)nnz);
+  // head rows: the rows stored most often, summed per workgroup in LDS by the
+  // inner-step scatter
+  std::vector<int32_t> order(d);
+  for (int64_t r = 0; r < d; ++r) order[r] = (int32_t)r;
+  const int64_t hcap = std::min<int64_t>(d, lr::sp_head_cap(PC));
+  std::partial_sort(order.begin(), order.begin() + hcap, order.end(), [&](int32_t a, int32_t b) {
+    const int32_t ca = row_ptr[a + 1] - row_ptr[a], cb = row_ptr[b + 1] - row_ptr[b];
+    return ca != cb ? ca > cb : a < b;
+  });
+  int H = 0;
+  while (H < hcap && row_ptr[order[H] + 1] > row_ptr[order[H]]) ++H;
+  std::vector<int32_t> head_slot(d, -1), head_row(std::max(H, 1), 0);
+  for (int h = 0; h < H; ++h) {
+    head_slot[order[h]] = h;
+    head_row[h] = order[h];
+  }
+  void *rc = nullptr, *cb = nullptr, *hs = nullptr, *hr = nullptr, *pt = nullptr;
+  LR_CHECK(keep(&rc, row_chunk.size() * 4));
+  LR_CHECK(keep(&cb, chunk_beg.size() * 4));
+  LR_CHECK(keep(&hs, head_slot.size() * 4));
+  LR_CHECK(keep(&hr, head_row.size() * 4));
+  LR_CHECK(keep(&pt, (size_t)std::max<int64_t>(nch, 1) * PC * 8));
+  LR_HIP(hipMemcpyAsync(rc, row_chunk.data(), row_chunk.size() * 4, hipMemcpyHostToDevice, st));
+  LR_HIP(hipMemcpyAsync(cb, chunk_beg.data(), chunk_beg.size() * 4, hipMemcpyHostToDevice, st));
+  LR_HIP(hipMemcpyAsync(hs, head_slot.data(), head_slot.size() * 4, hipMemcpyHostToDevice, st));
+  LR_HIP(hipMemcpyAsync(hr, head_row.data(), head_row.size() * 4, hipMemcpyHostToDevice, st));
+  LR_HIP(hipStreamSynchronize(st));
+  R = lr::CsrView{(const int32_t*)col, val, (const int32_t*)cb, (const int32_t*)rc, d, nch,
+                  Xs.dt};
+  sp_head_slot = (int32_t*)hs;
+  sp_head_row = (int32_t*)hr;
+  sp_H = H;
+  sp_part = (double*)pt;
+  return LR_OK;
+}
+
 namespace lr {
 
 lr_status plan_check(const lr_matrix* Xm, int k, int p, double eps, const lr_options* opt) {
   if (!Xm || !Xm->values) return fail(LR_EINVAL, "null matrix");
-  if (Xm->layout != LR_DENSE_COLMAJOR) return fail(LR_EINVAL, "only dense column-major X");
+  if (Xm->layout != LR_DENSE_COLMAJOR && Xm->layout != LR_CSC)
+    return fail(LR_EINVAL, "unknown layout");
   if (Xm->dtype < LR_F64 || Xm->dtype > LR_BF16) return fail(LR_EINVAL, "bad dtype");
   const int64_t d = Xm->d, n = Xm->n;
-  if (d < 2 || n < 1 || Xm->ld < d) return fail(LR_EINVAL, "bad sizes");
+  if (Xm->layout == LR_CSC) {
+    if (!Xm->col_ptr || !Xm->row_idx) return fail(LR_EINVAL, "null CSC index array");
+    if (d < 2 || n < 1 || Xm->nnz < 0 || Xm->nnz > 0x7fffffff)
+      return fail(LR_EINVAL, "bad sizes");
+  } else if (d < 2 || n < 1 || Xm->ld < d) {
+    return fail(LR_EINVAL, "bad sizes");
+  }
   if (!(1 <= k && k < p && p < d) || p > n || p > LR_MAX_P)
     return fail(LR_EINVAL, "need 1 <= k < p < d, p <= n, p <= 64");
   if (d > 0x7fffffff || n > 0x7fffffff) return fail(LR_EINVAL, "d and n must fit in int32");
@@ -467,14 +615,28 @@ lr_status plan_check(const lr_matrix* Xm, int k, int p, double eps, const lr_opt
 namespace {
 // Fill the size fields of a plan for X, k, p (no allocation).
 void plan_shape(lr_plan_s* pl, const lr_matrix* Xm, int k, int p) {
-  pl->X = lr::XView{Xm->values, Xm->d, Xm->n, Xm->ld, Xm->dtype};
+  pl->sparse = Xm->layout == LR_CSC;
+  pl->X = lr::XView{Xm->values, Xm->d, Xm->n, pl->sparse ? Xm->d : Xm->ld, Xm->dtype};
+  pl->Xs = lr::CscView{Xm->values, Xm->col_ptr, Xm->row_idx, Xm->d, Xm->n, Xm->nnz, Xm->dtype};
   pl->k = k;
   pl->p = p;
   pl->d = Xm->d;
   pl->n = Xm->n;
   pl->bmax = std::min<int64_t>(Xm->n, 8192);
   pl->PC = lr::pad16(p);
-  pl->pb.nsplit = lr::pass_nsplit(Xm->d, Xm->n);
+  pl->pb.nsplit = pl->sparse ? 0 : lr::pass_nsplit(Xm->d, Xm->n);
+}
+
+// Device bytes the compressed-column path keeps besides the carved block: the
+// row-ordered copy (column ids and values), chunk tables, head-row map and the
+// chunk partial sums (at most d + nnz / SP_CHUNK chunks).
+size_t sparse_extra_bytes(const lr_plan_s* pl) {
+  if (!pl->sparse) return 0;
+  const int64_t nnz = pl->Xs.nnz, d = pl->d;
+  const size_t elt = pl->Xs.dt == LR_F64 ? 8 : pl->Xs.dt == LR_F32 ? 4 : 2;
+  const int64_t nch = d + nnz / lr::SP_CHUNK + 1;
+  return (size_t)nnz * (4 + elt) + (size_t)(d + 1 + nch + 1 + d + 1024) * 4 +
+         (size_t)nch * pl->PC * 8;
 }
 }  // namespace
 
@@ -484,7 +646,7 @@ lr_status plan_bytes(const lr_matrix* Xm, int k, int p, const lr_options* opt, s
   tmp.owns_ws = false;
   tmp.owns_host = false;
   plan_shape(&tmp, Xm, k, p);
-  *bytes = tmp.carve(nullptr);
+  *bytes = tmp.carve(nullptr) + sparse_extra_bytes(&tmp);
   return LR_OK;
 }
 
@@ -533,6 +695,7 @@ lr_status plan_make(lr_plan_s** out, const lr_matrix* Xm, int k, int p, double e
   } else if (s == LR_OK) {
     s = host_res_create(&pl->hpin, pl->ev);
   }
+  if (s == LR_OK && pl->sparse) s = pl->sparse_setup();
   if (s != LR_OK) {
     delete pl;
     return s;

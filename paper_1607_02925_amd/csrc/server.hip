@@ -201,6 +201,8 @@ lr_status lowrank_submit(lr_server sv, const lr_matrix* X, int k, int p, double 
                          uint64_t* ticket) {
   if (!sv || !ticket) return fail(LR_EINVAL, "null argument");
   *ticket = 0;
+  if (X && X->layout != LR_DENSE_COLMAJOR)
+    return fail(LR_EINVAL, "the server takes dense column-major X");
   lr_status s = lr::plan_check(X, k, p, eps, opt);
   if (s != LR_OK) return s;
   size_t bytes = 0;

@@ -183,7 +183,44 @@ class Schedule:
         return s, arr
 
 
+class CscMatrix:
+    """Compressed-column X (d x n) on the device: col_ptr (int32, n + 1),
+    row_idx (int32, nnz; increasing within each column) and values (float64,
+    float32 or bfloat16, nnz)."""
+
+    def __init__(self, d, n, col_ptr, row_idx, values):
+        import torch
+        for t in (col_ptr, row_idx, values):
+            if not t.is_cuda or t.dim() != 1 or not t.is_contiguous():
+                raise ValueError("CSC arrays must be contiguous 1-D device tensors")
+        if col_ptr.dtype != torch.int32 or row_idx.dtype != torch.int32:
+            raise ValueError("col_ptr and row_idx must be int32")
+        if col_ptr.numel() != n + 1 or row_idx.numel() != values.numel():
+            raise ValueError("CSC array sizes do not match")
+        self.d, self.n = int(d), int(n)
+        self.col_ptr, self.row_idx, self.values = col_ptr, row_idx, values
+        self.nnz = values.numel()
+        self.device = values.device
+        self.shape = (self.n, self.d)     # as the (n, d) view of dense X
+
+    @classmethod
+    def from_arrays(cls, d, n, col_ptr, row_idx, values, device="cuda"):
+        """From host arrays (values as float64/float32, or uint16 BF16 bits)."""
+        import torch
+        if values.dtype == np.uint16:
+            v = torch.from_numpy(np.ascontiguousarray(values).view(np.int16)).to(device)
+            v = v.view(torch.bfloat16)
+        else:
+            v = torch.from_numpy(np.ascontiguousarray(values)).to(device)
+        return cls(d, n, torch.from_numpy(np.ascontiguousarray(col_ptr, np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(row_idx, np.int32)).to(device), v)
+
+
 def _matrix(Xt):
+    if isinstance(Xt, CscMatrix):
+        return lr_matrix(d=Xt.d, n=Xt.n, ld=Xt.d, nnz=Xt.nnz, dtype=_dtype_code(Xt.values),
+                         layout=1, values=Xt.values.data_ptr(), col_ptr=Xt.col_ptr.data_ptr(),
+                         row_idx=Xt.row_idx.data_ptr())
     if not Xt.is_cuda or Xt.dim() != 2 or not Xt.is_contiguous():
         raise ValueError("X must be a contiguous 2-D device tensor of shape (n, d)")
     n, d = Xt.shape
@@ -222,7 +259,8 @@ def plan_bytes(Xt, k, p, **kw):
 
 class Plan:
     """A plan over a device matrix X given as an (n, d) C-contiguous tensor, i.e.
-    X (d x n) in column-major order; each row of the tensor is a data point."""
+    X (d x n) in column-major order (each row of the tensor is a data point), or
+    as a CscMatrix."""
 
     def __init__(self, Xt, k, p, eps, seed=0, shift_mode=0, est_iters=4, max_outer=2000,
                  max_epochs=60, max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0,

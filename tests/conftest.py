@@ -17,3 +17,14 @@ def pytest_configure(config):
 def gpu_available():
     import torch
     return torch.cuda.is_available()
+
+
+@pytest.fixture(scope="session")
+def torch_cuda():
+    """torch with the library loaded; skips without a GPU."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_02925_amd import lowrank
+    lowrank.load_library()
+    return torch

@@ -22,16 +22,6 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-@pytest.fixture(scope="module")
-def torch_cuda():
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_1607_02925_amd import lowrank
-    lowrank.load_library()
-    return torch
-
-
 def to_device(torch, xt, storage):
     if storage == "bf16":
         return torch.from_numpy(np.ascontiguousarray(xt).view(np.int16)).cuda().view(
