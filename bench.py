@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 WORKLOAD = "planted-2048x200000-f32"
+SPARSE_WORKLOAD = "zipf-50000x1000000-csc-f32"
 METRIC = "solves/s + HBM GB/s at ε=1e-4 (plain FP32 vs BF16 batched); p99 latency"
 
 
@@ -48,7 +49,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="solve",
-                    choices=["solve", "pass", "epoch", "copy", "serve"])
+                    choices=["solve", "pass", "epoch", "copy", "serve", "sparse"])
+    ap.add_argument("--sparse-workload", default=SPARSE_WORKLOAD)
+    ap.add_argument("--sparse-steps", type=int, default=200,
+                    help="sparse: inner steps timed (one epoch of this length)")
     ap.add_argument("--requests", type=int, default=512, help="serve: trace length")
     ap.add_argument("--slots", type=int, default=8, help="serve: concurrent worker slots")
     ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: HBM budget (GB)")
@@ -165,6 +169,64 @@ def serve_run(reqs, X, slots, budget, open_loop=False):
     return res, outs
 
 
+def sparse_bench(args, dev):
+    """Compressed-column workload: plan creation (row-ordered copy), the pass
+    X (X^T W) and inner steps at the minibatch size the method picks for it
+    (b = 8192), timed on the device.  A whole solve of this workload takes
+    hundreds of outer iterations of ~10^4 inner steps each, so it is measured
+    per pass and per step."""
+    import torch
+    import workloads
+    from paper_1607_02925_amd import lowrank
+    w = workloads.workload(args.sparse_workload)
+    X = lowrank.CscMatrix.from_arrays(w["d"], w["n"], w["col_ptr"], w["row_idx"], w["values"],
+                                      device=dev)
+    torch.cuda.synchronize()
+    d, p = w["d"], w["p"]
+    t0 = time.time()
+    plan = lowrank.Plan(X, w["k"], p, w["eps"], seed=w["solver_seed"])
+    torch.cuda.synchronize()
+    t_plan = time.time() - t0
+    _, _, fro2 = plan.prepare()
+    S = torch.linalg.qr(torch.randn((d, p), dtype=torch.float64, device=dev))[0]
+    for _ in range(6):                      # top Ritz value for a realistic shift
+        S = torch.linalg.qr(plan.apply_A(S))[0]
+    theta1 = float(torch.linalg.eigvalsh(S.T @ plan.apply_A(S))[-1])
+    Wm = torch.randn((d, p), dtype=torch.float64, device=dev)
+    plan.apply_A(Wm)
+    torch.cuda.synchronize()
+    reps = max(3, args.steps)
+    t = time.time()
+    for _ in range(reps):
+        plan.apply_A(Wm)
+    torch.cuda.synchronize()
+    ms_pass = (time.time() - t) / reps * 1e3
+    lam, mu, b = 1.05 * theta1, 0.05 * theta1, 8192
+    eta = min(1.0 / lam, mu * b / (4.0 * fro2 * theta1))
+    m = args.sparse_steps
+    plan.svrg_solve(S, lam, eta, 8, b, 1, 1)
+    torch.cuda.synchronize()
+    t = time.time()
+    plan.svrg_solve(S, lam, eta, m, b, 2, 1)
+    torch.cuda.synchronize()
+    ms_epoch = (time.time() - t) * 1e3
+    us_step = (ms_epoch - 2 * ms_pass) / m * 1e3
+    elt = w["values"].dtype.itemsize
+    csc_bytes = w["nnz"] * (elt + 4) + (w["n"] + 1) * 4
+    out = {"workload": args.sparse_workload, "d": d, "n": w["n"], "nnz": w["nnz"], "p": p,
+           "plan_s": t_plan, "pass_ms": ms_pass,
+           "pass_GBps_alg": (csc_bytes + 3 * d * p * 8) / (ms_pass * 1e-3) / 1e9,
+           "pass_gather_GBps": 2 * w["nnz"] * lowrank_pad16(p) * 8 / (ms_pass * 1e-3) / 1e9,
+           "theta1": theta1, "b": b, "epoch_steps": m, "epoch_ms": ms_epoch,
+           "step_us": us_step}
+    log("sparse: %s" % json.dumps(out))
+    return out
+
+
+def lowrank_pad16(p):
+    return (p + 15) // 16 * 16
+
+
 def serve_bench(args, dev):
     import torch
     import workloads
@@ -218,6 +280,10 @@ def main():
     if args.mode == "serve":
         out = serve_bench(args, dev)
         print(json.dumps({"mode": "serve", **out}), flush=True)
+        return
+    if args.mode == "sparse":
+        out = sparse_bench(args, dev)
+        print(json.dumps({"mode": "sparse", **out}), flush=True)
         return
     w = dict(workloads.WORKLOADS[args.workload])
     t0 = time.time()

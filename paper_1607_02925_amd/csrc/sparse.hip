@@ -193,24 +193,35 @@ __global__ __launch_bounds__(NT) void k_csr_chunk(const TX* __restrict__ val,
   }
 }
 
+// One workgroup per row: NG groups of PC lanes stride the row's chunks, then
+// the groups are added in group order (heavy rows own hundreds of chunks).
+template <int PC>
 __global__ __launch_bounds__(NT) void k_csr_rows(const double* __restrict__ part,
                                                  const int32_t* __restrict__ row_chunk, int64_t d,
-                                                 int p, int PC, double alpha,
+                                                 int p, double alpha,
                                                  const double* __restrict__ A, double beta,
                                                  const double* __restrict__ B, double gamma,
                                                  double* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (e >= d * p) return;
-  const int64_t r = e / p;
-  const int c = (int)(e % p);
-  double s = 0.0;
-  const int64_t c1 = row_chunk[r + 1];
-  for (int64_t ch = row_chunk[r]; ch < c1; ++ch) s += part[ch * PC + c];
-  const int64_t o = (int64_t)c * d + r;
-  double y = alpha * s;
-  if (A) y += beta * A[o];
-  if (B) y += gamma * B[o];
-  out[o] = y;
+  constexpr int NG = NT / PC;
+  __shared__ double red[NG * PC];
+  const int g = threadIdx.x / PC, c = threadIdx.x % PC;
+  const int64_t r = blockIdx.x;
+  if (g < NG) {
+    double s = 0.0;
+    const int64_t c1 = row_chunk[r + 1];
+    for (int64_t ch = row_chunk[r] + g; ch < c1; ch += NG) s += part[ch * PC + c];
+    red[g * PC + c] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < p) {
+    double s = 0.0;
+    for (int q = 0; q < NG; ++q) s += red[q * PC + threadIdx.x];
+    const int64_t o = (int64_t)threadIdx.x * d + r;
+    double y = alpha * s;
+    if (A) y += beta * A[o];
+    if (B) y += gamma * B[o];
+    out[o] = y;
+  }
 }
 
 __global__ __launch_bounds__(NT) void k_rm_decay(int64_t count, const double* __restrict__ Grm,
@@ -393,8 +404,10 @@ hipError_t csr_xt(const CsrView& R, const double* T, int PC, int p, double* part
                 R.col, R.chunk_beg, T, part);
     }));
   }
-  k_csr_rows<<<blocks(R.d * p), NT, 0, st>>>(part, R.row_chunk, R.d, p, PC, alpha, A, beta, B,
-                                              gamma, out);
+  SP_DISPATCH_PC(PC, PCT, {
+    k_csr_rows<PCT><<<dim3((unsigned)R.d), NT, 0, st>>>(part, R.row_chunk, R.d, p, alpha, A, beta,
+                                                        B, gamma, out);
+  });
   return hipGetLastError();
 }
 
