@@ -123,7 +123,18 @@ typedef struct lr_schedule {
  *                   shift and deciding when to stop (lambda, mu_hat, eta, m, b,
  *                   first_solve, outer and epochs are used)
  *   timing          1: record HIP events around passes and inner-step loops
- *                   and report their durations in lr_report */
+ *                   and report their durations in lr_report
+ *   precision       LR_PREC_F64 (default): all arithmetic FP64.
+ *                   LR_PREC_BF16_STEPS (dense BF16 X only, else LR_EINVAL): the
+ *                   inner minibatch steps run on BF16 matrix cores, their FP64
+ *                   operands carried as hi + lo BF16 parts with FP32
+ *                   accumulation; the full-gradient passes that start every
+ *                   epoch, Cholesky-QR, Rayleigh-Ritz and the shift/gap
+ *                   estimates stay FP64, so each inner solve is refined against
+ *                   exactly computed residuals.  Results agree with the FP64
+ *                   form to the accuracy of the solve, not bit for bit. */
+typedef enum { LR_PREC_F64 = 0, LR_PREC_BF16_STEPS = 1 } lr_precision;
+
 typedef struct lr_options {
   uint64_t seed;
   int32_t shift_mode;
@@ -132,6 +143,7 @@ typedef struct lr_options {
   double eta_scale, tau_shift;
   const lr_schedule* replay;
   int32_t timing;
+  int32_t precision;      /* lr_precision */
 } lr_options;
 
 /* What a solve did.  Host struct filled by lowrank_solve. */

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "bf16.h"
 #include "kernels.h"
 #include "sparse.h"
 
@@ -65,6 +66,11 @@ struct lr_plan_s {
   int sp_H = 0;
   double* sp_part = nullptr;
   double *Wrm = nullptr, *Grm = nullptr, *Dlrm = nullptr;
+  // BF16 matrix-core inner steps: split copies of the difference block (ldD x PC)
+  // and of the sampled products (PC x ldC)
+  bool bf16_steps = false;
+  int64_t ldD = 0, ldC = 0;
+  uint16_t *Dh = nullptr, *Dlo = nullptr, *Ch = nullptr, *Cl = nullptr;
   int k = 0, p = 0;
   double eps = 0;
   lr_options opt{};
@@ -224,6 +230,10 @@ struct lr_plan_s {
     double r = r0;
     if (hist) hist->push_back(r);
     const uint32_t w3 = stream_word(TAG_SAMPLES, (uint32_t)solve);
+    if (bf16_steps) {   // sample slots beyond b stay zero for the whole solve
+      LR_HIP(hipMemsetAsync(Ch, 0, ldC * PC * sizeof(uint16_t), st));
+      LR_HIP(hipMemsetAsync(Cl, 0, ldC * PC * sizeof(uint16_t), st));
+    }
     int32_t e = 0;
     for (;;) {
       if (fixed_epochs < 0) {
@@ -237,6 +247,10 @@ struct lr_plan_s {
         LR_HIP(hipMemsetAsync(Dlrm, 0, d * PC * sizeof(double), st));
       } else {
         LR_HIP(hipMemsetAsync(Dl, 0, cnt * sizeof(double), st));
+        if (bf16_steps) {
+          LR_HIP(hipMemsetAsync(Dh, 0, ldD * PC * sizeof(uint16_t), st));
+          LR_HIP(hipMemsetAsync(Dlo, 0, ldD * PC * sizeof(uint16_t), st));
+        }
       }
       if (opt.timing) LR_HIP(hipEventRecord(ev[0], st));
       const int64_t tprobe = m / 2;  // one launch per epoch is timed per kernel
@@ -259,6 +273,11 @@ struct lr_plan_s {
             LR_HIP(lr::rm_decay(d * PC, Grm, Dlrm, lam, eta, st));
             LR_HIP(lr::csc_step_scatter(Xs, b, it, C, PC, p, sp_head_slot, sp_head_row, sp_H,
                                         eta, Dlrm, st, pu));
+          } else if (bf16_steps) {
+            LR_HIP(lr::step_dot_bf16(X, p, b, it, scale + (t - t0) * b, Dh, Dlo, ldD, Ch, Cl,
+                                     ldC, PC, st, pd));
+            LR_HIP(lr::step_update_bf16(X, p, b, it, Ch, Cl, ldC, PC, G, Dl, Dh, Dlo, ldD, lam,
+                                        eta, st, pu));
           } else {
             LR_HIP(lr::step_dot(X, p, b, it, scale + (t - t0) * b, Dl, C, PC, st, pd));
             LR_HIP(lr::step_update(X, p, b, it, C, PC, G, Dl, lam, eta, st, pu));
@@ -468,6 +487,8 @@ size_t lr_plan_s::carve(char* base) {
   take(&V, d * k);
   take(&Vprev, d * k);
   for (double** b : {&Wrm, &Grm, &Dlrm}) take(b, sparse ? d * PC : 0);
+  for (uint16_t** b : {&Dh, &Dlo}) take(b, bf16_steps ? ldD * PC : 0);
+  for (uint16_t** b : {&Ch, &Cl}) take(b, bf16_steps ? ldC * PC : 0);
   take(&T, n * PC);
   take(&Ypart, (int64_t)pb.nsplit * dp);
   take(&C, bmax * PC);
@@ -602,6 +623,11 @@ lr_status plan_check(const lr_matrix* Xm, int k, int p, double eps, const lr_opt
   if (!(eps > 0)) return fail(LR_EINVAL, "eps must be positive");
   if (opt) {
     if (opt->batch < 0 || opt->batch > 8192) return fail(LR_EINVAL, "batch must be in [0, 8192]");
+    if (opt->precision < LR_PREC_F64 || opt->precision > LR_PREC_BF16_STEPS)
+      return fail(LR_EINVAL, "unknown precision");
+    if (opt->precision == LR_PREC_BF16_STEPS &&
+        (Xm->layout != LR_DENSE_COLMAJOR || Xm->dtype != LR_BF16))
+      return fail(LR_EINVAL, "BF16 matrix-core steps need dense BF16 X");
     if (opt->replay) {
       const lr_schedule* r = opt->replay;
       if (r->outer < 0 || (r->outer > 0 && !r->epochs) || r->b < 1 || r->b > n || r->b > 8192 ||
@@ -614,7 +640,7 @@ lr_status plan_check(const lr_matrix* Xm, int k, int p, double eps, const lr_opt
 
 namespace {
 // Fill the size fields of a plan for X, k, p (no allocation).
-void plan_shape(lr_plan_s* pl, const lr_matrix* Xm, int k, int p) {
+void plan_shape(lr_plan_s* pl, const lr_matrix* Xm, int k, int p, const lr_options* opt) {
   pl->sparse = Xm->layout == LR_CSC;
   pl->X = lr::XView{Xm->values, Xm->d, Xm->n, pl->sparse ? Xm->d : Xm->ld, Xm->dtype};
   pl->Xs = lr::CscView{Xm->values, Xm->col_ptr, Xm->row_idx, Xm->d, Xm->n, Xm->nnz, Xm->dtype};
@@ -625,6 +651,9 @@ void plan_shape(lr_plan_s* pl, const lr_matrix* Xm, int k, int p) {
   pl->bmax = std::min<int64_t>(Xm->n, 8192);
   pl->PC = lr::pad16(p);
   pl->pb.nsplit = pl->sparse ? 0 : lr::pass_nsplit(Xm->d, Xm->n);
+  pl->bf16_steps = opt && opt->precision == LR_PREC_BF16_STEPS;
+  pl->ldD = lr::pad_to(Xm->d, 32);
+  pl->ldC = lr::pad_to(pl->bmax, 32);
 }
 
 // Device bytes the compressed-column path keeps besides the carved block: the
@@ -645,7 +674,7 @@ lr_status plan_bytes(const lr_matrix* Xm, int k, int p, const lr_options* opt, s
   lr_plan_s tmp;
   tmp.owns_ws = false;
   tmp.owns_host = false;
-  plan_shape(&tmp, Xm, k, p);
+  plan_shape(&tmp, Xm, k, p, opt);
   *bytes = tmp.carve(nullptr) + sparse_extra_bytes(&tmp);
   return LR_OK;
 }
@@ -667,7 +696,7 @@ lr_status plan_make(lr_plan_s** out, const lr_matrix* Xm, int k, int p, double e
     pl->opt = *opt;
   else
     lowrank_options_default(&pl->opt);
-  plan_shape(pl, Xm, k, p);
+  plan_shape(pl, Xm, k, p, &pl->opt);
   if (pl->opt.replay) {
     const lr_schedule* r = pl->opt.replay;
     pl->replay = true;
@@ -757,6 +786,7 @@ void lowrank_options_default(lr_options* o) {
   o->tau_shift = 1e-2;
   o->replay = nullptr;
   o->timing = 0;
+  o->precision = LR_PREC_F64;
 }
 
 lr_status lowrank_plan(lr_plan* out, const lr_matrix* Xm, int k, int p, double eps,

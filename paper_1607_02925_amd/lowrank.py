@@ -19,6 +19,7 @@ LR_MAX_P = 64
 LR_MAX_SHIFT_ROUNDS = 64
 LR_MAX_SLOTS = 16
 LR_F64, LR_F32, LR_BF16 = 0, 1, 2
+LR_PREC_F64, LR_PREC_BF16_STEPS = 0, 1
 
 
 class lr_matrix(ctypes.Structure):
@@ -42,7 +43,8 @@ class lr_options(ctypes.Structure):
                 ("max_epochs", ctypes.c_int32), ("max_shift_rounds", ctypes.c_int32),
                 ("polish", ctypes.c_int32), ("batch", ctypes.c_int64),
                 ("eta_scale", ctypes.c_double), ("tau_shift", ctypes.c_double),
-                ("replay", ctypes.POINTER(lr_schedule)), ("timing", ctypes.c_int32)]
+                ("replay", ctypes.POINTER(lr_schedule)), ("timing", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
 
 
 class lr_report(ctypes.Structure):
@@ -230,7 +232,7 @@ def _matrix(Xt):
 
 def make_options(seed=0, shift_mode=0, est_iters=4, max_outer=2000, max_epochs=60,
                  max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0, tau_shift=1e-2,
-                 replay=None, timing=0):
+                 replay=None, timing=0, precision=0):
     """lr_options plus the host objects it points to (kept alive by the caller)."""
     lib = load_library()
     opt = lr_options()
@@ -239,6 +241,7 @@ def make_options(seed=0, shift_mode=0, est_iters=4, max_outer=2000, max_epochs=6
     opt.shift_mode, opt.est_iters, opt.max_outer = shift_mode, est_iters, max_outer
     opt.max_epochs, opt.max_shift_rounds, opt.polish = max_epochs, max_shift_rounds, polish
     opt.batch, opt.eta_scale, opt.tau_shift, opt.timing = batch, eta_scale, tau_shift, timing
+    opt.precision = precision
     keep = None
     if replay is not None:
         sc, arr = replay.to_c()
@@ -264,7 +267,7 @@ class Plan:
 
     def __init__(self, Xt, k, p, eps, seed=0, shift_mode=0, est_iters=4, max_outer=2000,
                  max_epochs=60, max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0,
-                 tau_shift=1e-2, replay=None, timing=0):
+                 tau_shift=1e-2, replay=None, timing=0, precision=0):
         import torch
         self.lib = load_library()
         self._mat = _matrix(Xt)
@@ -275,7 +278,8 @@ class Plan:
         opt, self._replay_keep = make_options(
             seed=seed, shift_mode=shift_mode, est_iters=est_iters, max_outer=max_outer,
             max_epochs=max_epochs, max_shift_rounds=max_shift_rounds, polish=polish, batch=batch,
-            eta_scale=eta_scale, tau_shift=tau_shift, replay=replay, timing=timing)
+            eta_scale=eta_scale, tau_shift=tau_shift, replay=replay, timing=timing,
+            precision=precision)
         self._opt = opt
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

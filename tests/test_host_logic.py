@@ -74,3 +74,29 @@ def test_server_argument_checks_without_gpu(lib):
     assert lib.lowrank_poll(None, 1, None, None) == lowrank.LR_EINVAL
     assert lib.lowrank_wait(None, 1, None, None) == lowrank.LR_EINVAL
     lib.lowrank_server_destroy(None)
+
+
+def test_precision_option_checks(lib):
+    """The BF16 matrix-core steps are offered for dense BF16 X only; the check
+    happens before any device call."""
+    from paper_1607_02925_amd import lowrank
+    h = ctypes.c_void_p()
+    opt = lowrank.lr_options()
+    lib.lowrank_options_default(ctypes.byref(opt))
+    assert opt.precision == lowrank.LR_PREC_F64
+    opt.precision = lowrank.LR_PREC_BF16_STEPS
+    m = _mat(100, 500, dtype=lowrank.LR_F32)
+    assert lib.lowrank_plan(ctypes.byref(h), ctypes.byref(m), 2, 4, 1e-4, ctypes.byref(opt),
+                            None) == lowrank.LR_EINVAL
+    assert b"BF16" in lib.lowrank_last_error()
+    opt.precision = 7
+    m = _mat(100, 500, dtype=lowrank.LR_BF16)
+    assert lib.lowrank_plan(ctypes.byref(h), ctypes.byref(m), 2, 4, 1e-4, ctypes.byref(opt),
+                            None) == lowrank.LR_EINVAL
+    # the split copies add to the workspace
+    out0, out1 = ctypes.c_size_t(), ctypes.c_size_t()
+    opt.precision = lowrank.LR_PREC_F64
+    assert lib.lowrank_plan_bytes(ctypes.byref(m), 2, 4, ctypes.byref(opt), ctypes.byref(out0)) == 0
+    opt.precision = lowrank.LR_PREC_BF16_STEPS
+    assert lib.lowrank_plan_bytes(ctypes.byref(m), 2, 4, ctypes.byref(opt), ctypes.byref(out1)) == 0
+    assert out1.value > out0.value
