@@ -49,10 +49,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="solve",
-                    choices=["solve", "pass", "epoch", "copy", "serve", "sparse"])
+                    choices=["solve", "pass", "epoch", "copy", "serve", "sparse", "steps"])
     ap.add_argument("--sparse-workload", default=SPARSE_WORKLOAD)
     ap.add_argument("--sparse-steps", type=int, default=200,
-                    help="sparse: inner steps timed (one epoch of this length)")
+                    help="sparse/steps: inner steps timed (one epoch of this length)")
+    ap.add_argument("--precision", type=int, default=0,
+                    help="0: FP64 arithmetic; 1: BF16 matrix-core inner steps (BF16 X)")
+    ap.add_argument("--batch", type=int, default=0, help="steps: minibatch size (0: 4096)")
     ap.add_argument("--requests", type=int, default=512, help="serve: trace length")
     ap.add_argument("--slots", type=int, default=8, help="serve: concurrent worker slots")
     ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: HBM budget (GB)")
@@ -223,6 +226,47 @@ def sparse_bench(args, dev):
     return out
 
 
+def steps_bench(args, dev):
+    """Dense workload: one pass and one epoch of --sparse-steps inner steps at
+    minibatch b (default 4096) in the chosen precision, with a shift 5% above
+    the top Ritz value of six power steps."""
+    import torch
+    import workloads
+    from paper_1607_02925_amd import lowrank
+    w = dict(workloads.WORKLOADS[args.workload])
+    data = workloads.workload(args.workload, device=dev)
+    Xt = data["Xt"]
+    torch.cuda.synchronize()
+    d, p = w["d"], w["p"]
+    plan = lowrank.Plan(Xt, w["k"], p, w["eps"], seed=w["solver_seed"], precision=args.precision)
+    _, _, fro2 = plan.prepare()
+    S = torch.linalg.qr(torch.randn((d, p), dtype=torch.float64, device=dev))[0]
+    for _ in range(6):
+        S = torch.linalg.qr(plan.apply_A(S))[0]
+    theta1 = float(torch.linalg.eigvalsh(S.T @ plan.apply_A(S))[-1])
+    torch.cuda.synchronize()
+    reps = max(3, args.steps)
+    t = time.time()
+    for _ in range(reps):
+        plan.apply_A(S)
+    torch.cuda.synchronize()
+    ms_pass = (time.time() - t) / reps * 1e3
+    lam, mu, b = 1.05 * theta1, 0.05 * theta1, args.batch or 4096
+    eta = min(1.0 / lam, mu * b / (4.0 * fro2 * theta1))
+    m = args.sparse_steps
+    plan.svrg_solve(S, lam, eta, 8, b, 1, 1)
+    torch.cuda.synchronize()
+    t = time.time()
+    plan.svrg_solve(S, lam, eta, m, b, 2, 1)
+    torch.cuda.synchronize()
+    ms_epoch = (time.time() - t) * 1e3
+    out = {"workload": args.workload, "precision": args.precision, "d": d, "n": w["n"], "p": p,
+           "b": b, "pass_ms": ms_pass, "epoch_steps": m, "epoch_ms": ms_epoch,
+           "step_us": (ms_epoch - 2 * ms_pass) / m * 1e3}
+    log("steps: %s" % json.dumps(out))
+    return out
+
+
 def lowrank_pad16(p):
     return (p + 15) // 16 * 16
 
@@ -284,6 +328,10 @@ def main():
     if args.mode == "sparse":
         out = sparse_bench(args, dev)
         print(json.dumps({"mode": "sparse", **out}), flush=True)
+        return
+    if args.mode == "steps":
+        out = steps_bench(args, dev)
+        print(json.dumps({"mode": "steps", **out}), flush=True)
         return
     w = dict(workloads.WORKLOADS[args.workload])
     t0 = time.time()
