@@ -395,26 +395,32 @@ __device__ __forceinline__ void waves_to_lds_seq(double* red, const v4d* acc, in
 // out[c * PC + 16 (NTW y + u) + j] = scale_c * sum_r X[r, col(c)] M[r, 16 (NTW y + u) + j]
 // for c < ncols, j < 16, u < NTW, y = blockIdx.y.  col(c) = idx[c] (GATHER)
 // or c.  M: d x p, column-major, leading dim d; columns >= p count as zero.
-// A workgroup owns 16 columns of X and NTW 16-column slices of M; its NW
-// waves split the rows.  Each wave issues the loads of G 16-row blocks before
-// it starts their matrix-core work, so G memory latencies overlap.
-template <typename TX, int NW, int NTW, int G, bool GATHER, bool VEC>
+// A workgroup owns MT tiles of 16 columns of X and NTW 16-column slices of M
+// (each M fetch feeds MT tiles); its NW waves split the rows.  Each wave
+// issues the loads of G 16-row blocks before it starts their matrix-core
+// work, so G memory latencies overlap.
+template <typename TX, int NW, int NTW, int G, bool GATHER, bool VEC, int MT = 1>
 __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64_t ld, int64_t d,
                                                  int64_t ncols, const int32_t* __restrict__ idx,
                                                  const double* __restrict__ M, int p,
                                                  const double* __restrict__ scale,
                                                  double* __restrict__ out, int PC, bool mvec) {
-  __shared__ double red[NTW * 256];
-  __shared__ double slots[NW * NTW * 256];
+  __shared__ double red[MT * NTW * 256];
+  __shared__ double slots[MT == 1 ? NW * NTW * 256 : 1];
   const int t = threadIdx.x, wave = t / 64, l = t % 64;
   const int li = l % 16, q = l / 16;
   const int64_t tile = blockIdx.x;
   const int nt0 = blockIdx.y * NTW;
-  const int64_t c = tile * 16 + li;
-  const bool cval = c < ncols;
-  int64_t colidx = 0;
-  if (cval) colidx = GATHER ? (int64_t)idx[c] : c;
-  const TX* xcol = X + colidx * ld;
+  bool cval[MT];
+  const TX* xcol[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int64_t c = (tile * MT + mt) * 16 + li;
+    cval[mt] = c < ncols;
+    int64_t colidx = 0;
+    if (cval[mt]) colidx = GATHER ? (int64_t)idx[c] : c;
+    xcol[mt] = X + colidx * ld;
+  }
   const double* mc[NTW];
   bool jval[NTW];
 #pragma unroll
@@ -423,23 +429,26 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
     jval[u] = j < p;
     mc[u] = M + (int64_t)(jval[u] ? j : 0) * d;
   }
-  v4d acc[NTW];
+  v4d acc[MT * NTW];
 #pragma unroll
-  for (int u = 0; u < NTW; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int a = 0; a < MT * NTW; ++a) acc[a] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t nblk = (d + 15) / 16;
   const int64_t bpw = (nblk + NW - 1) / NW;
   const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
   for (int64_t g0 = b0; g0 < b1; g0 += G) {
-    Raw4<TX> x[G];
+    Raw4<TX> x[G][MT];
     double m[G][NTW][4];
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       const int64_t r = (g0 + i) * 16 + 4 * q;
       const bool bval = g0 + i < b1;
-      if (bval && cval)
-        load4raw<TX, VEC>(xcol, r, d, x[i]);
-      else
-        x[i].zero();
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        if (bval && cval[mt])
+          load4raw<TX, VEC>(xcol[mt], r, d, x[i][mt]);
+        else
+          x[i][mt].zero();
+      }
 #pragma unroll
       for (int u = 0; u < NTW; ++u) {
         if (bval && jval[u]) {
@@ -459,14 +468,20 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
 #pragma unroll
     for (int i = 0; i < G; ++i)
 #pragma unroll
-      for (int u = 0; u < NTW; ++u)
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc[u] = mfma_f64(x[i].get(s), m[i][u][s], acc[u]);
+        for (int u = 0; u < NTW; ++u)
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            acc[mt * NTW + u] = mfma_f64(x[i][mt].get(s), m[i][u][s], acc[mt * NTW + u]);
   }
-  waves_to_lds<NW, NTW>(red, slots, acc, q, li);
-  for (int e = t; e < NTW * 256; e += NW * 64) {
-    const int u = e / 256, i = (e / 16) % 16, jj = e % 16;
-    const int64_t cc = tile * 16 + i;
+  if constexpr (MT == 1)
+    waves_to_lds<NW, NTW>(red, slots, acc, q, li);
+  else
+    waves_to_lds_seq<NW, MT * NTW>(red, acc, q, li);
+  for (int e = t; e < MT * NTW * 256; e += NW * 64) {
+    const int a = e / 256, mt = a / NTW, u = a % NTW, i = (e / 16) % 16, jj = e % 16;
+    const int64_t cc = (tile * MT + mt) * 16 + i;
     if (cc < ncols && (nt0 + u) * 16 < PC) {
       const double sc = scale ? scale[cc] : 1.0;
       out[cc * PC + (nt0 + u) * 16 + jj] = sc * red[e];
@@ -568,7 +583,12 @@ __global__ __launch_bounds__(NW * 64) void k_step_update(const TX* __restrict__ 
   __shared__ int sidx[KSTAGE];
   const int t = threadIdx.x, wave = t / 64, l = t % 64;
   const int lm = l % 16, q = l / 16;
-  const int64_t r0 = (int64_t)blockIdx.x * 16;
+  // Workgroups go to the 8 XCDs in turn; the grid (a multiple of 8 tiles) is
+  // remapped so each XCD owns a contiguous run of row tiles, and the two
+  // 64-byte halves of a 128-byte line of a gathered column meet in one L2.
+  const int64_t tile = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  const int64_t r0 = tile * 16;
+  if (r0 >= d) return;
   const int nt0 = blockIdx.y * NTW;
   // the epilogue's operands are fetched now, so their latency overlaps the loop
   double e_dl[NTW], e_g[NTW];
@@ -1152,31 +1172,35 @@ int pass_nsplit(int64_t d, int64_t n) {
   return (int)clampi((2048 + tiles - 1) / tiles, 1, std::max<int64_t>(1, (n + 127) / 128));
 }
 
-template <int NW, int NTW, int G, bool GATHER>
+template <int NW, int NTW, int G, bool GATHER, int MT = 1>
 static hipError_t launch_xtm(const XView& X, int64_t ncols, const int32_t* idx, const double* M,
                              int p, const double* scale, double* out, int PC, hipStream_t st,
                              const Probe& pr) {
   const bool vec = x_vec_ok(X);
   const bool mvec = X.d % 2 == 0 && (uintptr_t)M % 16 == 0;  // M columns start 16-B aligned
   const int nt = (p + 15) / 16;
-  dim3 grid((unsigned)((ncols + 15) / 16), (unsigned)((nt + NTW - 1) / NTW));
+  dim3 grid((unsigned)((ncols + 16 * MT - 1) / (16 * MT)), (unsigned)((nt + NTW - 1) / NTW));
   LR_DISPATCH_DT(X.dt, TX, {
     if (vec)
-      launch(k_xtm<TX, NW, NTW, G, GATHER, true>, grid, dim3(NW * 64), st, pr, (const TX*)X.v,
-             X.ld, X.d, ncols, idx, M, p, scale, out, PC, mvec);
+      launch(k_xtm<TX, NW, NTW, G, GATHER, true, MT>, grid, dim3(NW * 64), st, pr,
+             (const TX*)X.v, X.ld, X.d, ncols, idx, M, p, scale, out, PC, mvec);
     else
-      launch(k_xtm<TX, NW, NTW, G, GATHER, false>, grid, dim3(NW * 64), st, pr, (const TX*)X.v,
-             X.ld, X.d, ncols, idx, M, p, scale, out, PC, mvec);
+      launch(k_xtm<TX, NW, NTW, G, GATHER, false, MT>, grid, dim3(NW * 64), st, pr,
+             (const TX*)X.v, X.ld, X.d, ncols, idx, M, p, scale, out, PC, mvec);
   });
   return hipGetLastError();
 }
 
+// The pass reads every column once; MT column tiles per workgroup share each
+// fetch of W.
 hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, hipStream_t st,
                     const Probe& pr) {
   if (p > 64 || pad16(p) > PC) return hipErrorInvalidValue;
-  if (p > 32) return launch_xtm<8, 4, 2, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st, pr);
-  if (p > 16) return launch_xtm<8, 2, 4, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st, pr);
-  return launch_xtm<8, 1, 4, false>(X, X.n, nullptr, W, p, nullptr, T, PC, st, pr);
+  if (p > 32)
+    return launch_xtm<8, 4, 2, false, 2>(X, X.n, nullptr, W, p, nullptr, T, PC, st, pr);
+  if (p > 16)
+    return launch_xtm<8, 2, 2, false, 4>(X, X.n, nullptr, W, p, nullptr, T, PC, st, pr);
+  return launch_xtm<8, 1, 4, false, 4>(X, X.n, nullptr, W, p, nullptr, T, PC, st, pr);
 }
 
 hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBufs& pb,
@@ -1219,7 +1243,7 @@ hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, con
   if (p > 64 || b > KSTAGE || pad16(p) != PC) return hipErrorInvalidValue;
   // one 16-column slice per workgroup: twice the gathers of one slice per
   // row tile, but twice the workgroups, which this latency-bound step needs
-  dim3 grid((unsigned)((X.d + 15) / 16), (unsigned)((p + 15) / 16));
+  dim3 grid((unsigned)(((X.d + 15) / 16 + 7) / 8 * 8), (unsigned)((p + 15) / 16));
   LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV,
       launch(k_step_update<TX, 16, 4, 16 * NTV, 1>, grid, dim3(1024), st, pr, (const TX*)X.v,
              X.ld, X.d, b, idx, C, p, G, Dl, lam, eta)));
