@@ -17,3 +17,7 @@ from .lowrank import (  # noqa: F401
     solver_constants, svrg_step, svrg_solve, tune_shift, si_iterate, final_rr,
     LR_OK, LR_EINVAL, LR_ENOMEM, LR_ENOGAP, LR_ENOCONV, LR_ESHIFT, LR_ENOTSPD,
 )
+from .adaptive import (  # noqa: F401
+    solve_adaptive, large_detect, delta_detect, estimate_deflated, power_deflated, si_deflated,
+)
+from .lowrank import deflate  # noqa: F401

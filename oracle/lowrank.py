@@ -107,9 +107,20 @@ def decode(xt, storage):
     return np.asarray(xt).astype(np.float64).T
 
 
-def apply_A(X, W):
-    """A W = X (X^T W); A = XX^T is never formed (Section 2.2.1 footnote)."""
-    return X @ (X.T @ W)
+def deflate(Ud, W):
+    """(I - Ud Ud^T) W: the projection that removes the directions already
+    found (Section 3.1, the deflated matrices A_{-(s-1)} and D_{-(s-1)})."""
+    if Ud is None or Ud.shape[1] == 0:
+        return W
+    return W - Ud @ (Ud.T @ W)
+
+
+def apply_A(X, W, Ud=None):
+    """A W = X (X^T W); A = XX^T is never formed (Section 2.2.1 footnote).
+    With a deflation basis Ud: the deflated A_{-(s-1)} = P A P, P = I - Ud Ud^T."""
+    if Ud is None:
+        return X @ (X.T @ W)
+    return deflate(Ud, X @ (X.T @ deflate(Ud, W)))
 
 
 def estimate_phase(X, k, p, seed, est_iters):
@@ -143,23 +154,25 @@ def solver_constants(fro2, theta1, lam, mu_hat, n, batch=0, eta_scale=1.0):
     return b, eta, m
 
 
-def svrg_step(X, W, Wt, G, lam, eta, idx, scale):
+def svrg_step(X, W, Wt, G, lam, eta, idx, scale, Ud=None):
     """One minibatch step: with Delta = W - W~ and the sampled columns X_B,
     W <- W - eta (G~ + lam Delta - X_B diag(scale) X_B^T Delta), where
     G~ = lam W~ - XX^T W~ - S is the full gradient at the epoch's anchor W~ and
-    scale_j = 1 / (b pi_j)."""
+    scale_j = 1 / (b pi_j).  Deflated (Ud given): the sampled columns are those
+    of P X, P = I - Ud Ud^T; Delta stays in the range of P, so only the product
+    X_B C is projected."""
     Xb = X[:, idx]
     Dl = W - Wt
     C = (Xb.T @ Dl) * scale[:, None]
-    return W - eta * (G + lam * Dl - Xb @ C)
+    return W - eta * (G + lam * Dl - deflate(Ud, Xb @ C))
 
 
 def svrg_solve(X, qc, S, lam, eta, m, b, tau, seed, solve, max_epochs,
-               fixed_epochs=None):
+               fixed_epochs=None, Ud=None):
     """Approximately solve (lam I - XX^T) W = S.  Returns (W, epochs, residual
     norms per epoch).  Warm start W0 = S (lam I - S^T A S)^{-1}, whose gradient
     (lam S - AS) M - S needs no extra pass."""
-    Y = apply_A(X, S)
+    Y = apply_A(X, S, Ud)
     H = S.T @ Y
     H = 0.5 * (H + H.T)
     p = S.shape[1]
@@ -180,9 +193,9 @@ def svrg_solve(X, qc, S, lam, eta, m, b, tau, seed, solve, max_epochs,
             break
         for t in range(m):
             idx, sc = step_indices(seed, solve, e, t, b, qc)
-            W = svrg_step(X, W, Wt, G, lam, eta, idx, sc)
+            W = svrg_step(X, W, Wt, G, lam, eta, idx, sc, Ud)
         Wt = W
-        G = lam * Wt - apply_A(X, Wt) - S
+        G = lam * Wt - apply_A(X, Wt, Ud) - S
         e += 1
         res.append(np.linalg.norm(G))
         if not np.isfinite(res[-1]) or res[-1] > 1e3 * res[0]:
@@ -190,9 +203,11 @@ def svrg_solve(X, qc, S, lam, eta, m, b, tau, seed, solve, max_epochs,
     return Wt, e, res
 
 
-def tune_shift(X, qc, S_est, theta, res, delta, fro2, seed, opt, n):
+def tune_shift(X, qc, S_est, theta, res, delta, fro2, seed, opt, n, Ud=None, solve0=0,
+               out=None):
     """Alg. shiftTune on the estimate-phase block.  Returns (lam, mu_hat,
-    rounds, history)."""
+    rounds, history).  Ud: deflation basis; solve0: solve index of the first
+    round; out (dict): receives "nu", the Ritz values of the last round."""
     t1, r1 = theta[0], res[0]
     if opt.shift_mode == "literal":
         lam = 1.5 * t1
@@ -203,10 +218,13 @@ def tune_shift(X, qc, S_est, theta, res, delta, fro2, seed, opt, n):
     hist = []
     for r in range(opt.max_shift_rounds):
         b, eta, m = solver_constants(fro2, t1, lam, mu, n, opt.batch, opt.eta_scale)
-        W, _, _ = svrg_solve(X, qc, S_est, lam, eta, m, b, opt.tau_shift, seed, r,
-                             opt.max_epochs)
+        W, _, _ = svrg_solve(X, qc, S_est, lam, eta, m, b, opt.tau_shift, seed, solve0 + r,
+                             opt.max_epochs, Ud=Ud)
         K = S_est.T @ W
-        nu1 = eigh_desc(0.5 * (K + K.T))[0][0]
+        nu = eigh_desc(0.5 * (K + K.T))[0]
+        if out is not None:
+            out["nu"] = nu
+        nu1 = nu[0]
         if not nu1 > 0:
             raise LowRankError(LR_ESHIFT, "shift estimate not positive")
         g = 1.0 / nu1

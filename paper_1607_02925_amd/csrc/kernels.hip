@@ -570,7 +570,7 @@ __global__ __launch_bounds__(NT) void k_reduce_y(const double* __restrict__ part
 // Dl <- Dl - eta (G + lam Dl - U),  U[r, j] = sum_s X[r, idx[s]] C[s * PC + j].
 // The NW waves split the b samples (indices staged in LDS) and load G sample
 // blocks ahead.
-template <typename TX, int NW, int G, int PC, int NTW>
+template <typename TX, int NW, int G, int PC, int NTW, int KS>
 __global__ __launch_bounds__(NW * 64) void k_step_update(const TX* __restrict__ X, int64_t ld,
                                                          int64_t d, int64_t b,
                                                          const int32_t* __restrict__ idx,
@@ -580,7 +580,7 @@ __global__ __launch_bounds__(NW * 64) void k_step_update(const TX* __restrict__ 
                                                          double eta) {
   __shared__ double red[NTW * 256];
   __shared__ double slots[NW * NTW * 256];
-  __shared__ int sidx[KSTAGE];
+  __shared__ int sidx[KS];
   const int t = threadIdx.x, wave = t / 64, l = t % 64;
   const int lm = l % 16, q = l / 16;
   // Workgroups go to the 8 XCDs in turn; the grid (a multiple of 8 tiles) is
@@ -1231,9 +1231,15 @@ hipError_t draw_chunk(int64_t n, const uint64_t* cdf, uint64_t seed, uint32_t t0
   return hipGetLastError();
 }
 
+// Workgroup size follows the problem: each wave gets about one prefetch group
+// of 16-row blocks, so small problems launch small workgroups that share a CU
+// with the kernels of other requests instead of holding it alone.
 hipError_t step_dot(const XView& X, int p, int64_t b, const int32_t* idx, const double* scale,
                     const double* Dl, double* C, int PC, hipStream_t st, const Probe& pr) {
   if (p > 64 || pad16(p) > PC) return hipErrorInvalidValue;
+  const int64_t nblk = (X.d + 15) / 16;
+  if (nblk <= 16) return launch_xtm<4, 1, 4, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
+  if (nblk <= 32) return launch_xtm<8, 1, 4, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
   return launch_xtm<16, 1, 4, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
 }
 
@@ -1244,9 +1250,20 @@ hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, con
   // one 16-column slice per workgroup: twice the gathers of one slice per
   // row tile, but twice the workgroups, which this latency-bound step needs
   dim3 grid((unsigned)(((X.d + 15) / 16 + 7) / 8 * 8), (unsigned)((p + 15) / 16));
-  LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV,
-      launch(k_step_update<TX, 16, 4, 16 * NTV, 1>, grid, dim3(1024), st, pr, (const TX*)X.v,
-             X.ld, X.d, b, idx, C, p, G, Dl, lam, eta)));
+  // waves split the samples: as many as give each about one prefetch group
+  if (b <= 256) {
+    LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV,
+        launch(k_step_update<TX, 4, 4, 16 * NTV, 1, 256>, grid, dim3(256), st, pr,
+               (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta)));
+  } else if (b <= 512) {
+    LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV,
+        launch(k_step_update<TX, 8, 4, 16 * NTV, 1, 512>, grid, dim3(512), st, pr,
+               (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta)));
+  } else {
+    LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV,
+        launch(k_step_update<TX, 16, 4, 16 * NTV, 1, KSTAGE>, grid, dim3(1024), st, pr,
+               (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta)));
+  }
   return hipGetLastError();
 }
 
