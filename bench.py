@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--precision", type=int, default=0,
                     help="0: FP64 arithmetic; 1: BF16 matrix-core inner steps (BF16 X)")
     ap.add_argument("--batch", type=int, default=0, help="steps: minibatch size (0: 4096)")
+    ap.add_argument("--adaptive", type=int, default=0,
+                    help="solve: 1 = adaptive partitioning of Algorithm main")
     ap.add_argument("--requests", type=int, default=512, help="serve: trace length")
     ap.add_argument("--slots", type=int, default=8, help="serve: concurrent worker slots")
     ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: HBM budget (GB)")
@@ -133,6 +135,31 @@ def cpu_baseline(Xt_dev, w, sched, rep):
                       "X(X^T S) pass and one inner-solver epoch (m=%d steps, b=%d) timed, "
                       "scaled by the GPU run's %d passes and %d epochs per solve"
                       % (sched.m, sched.b, rep["passes"], rep["total_epochs"])}
+
+
+def adaptive_leg(Xt, w, U_qk, args):
+    """The same workload through the adaptive partitioning of Algorithm main
+    (lr_options.adaptive = 1): solves/s, the intervals it chose, and the
+    principal-angle sine between its U_k and the q = k branch's."""
+    import torch
+    from paper_1607_02925_amd import lowrank
+    plan = lowrank.Plan(Xt, w["k"], w["p"], w["eps"], seed=w["solver_seed"], adaptive=1)
+    plan.solve()
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(max(1, args.steps)):
+        t = time.time()
+        st, U, theta, rep = plan.solve()
+        torch.cuda.synchronize()
+        lat.append(time.time() - t)
+    Uq = U_qk.contiguous()
+    Ua = U.contiguous()
+    sin = float(torch.linalg.matrix_norm(Ua - Uq @ (Uq.T @ Ua), ord=2))
+    out = {"solves_per_s": len(lat) / sum(lat), "ms_per_solve": sum(lat) / len(lat) * 1e3,
+           "status": st, "passes": rep["passes"], "inner_steps": rep["steps"],
+           "intervals": rep["intervals"], "sin_vs_q_eq_k": sin}
+    log("adaptive: %s" % json.dumps(out))
+    return out
 
 
 def serve_run(reqs, X, slots, budget, open_loop=False):
@@ -356,7 +383,8 @@ def main():
                           "ms": dt * 1e3, "GBps": 2 * x_bytes / dt / 1e9}), flush=True)
         return
 
-    plan = lowrank.Plan(Xt, k, p, w["eps"], seed=w["solver_seed"], timing=1)
+    plan = lowrank.Plan(Xt, k, p, w["eps"], seed=w["solver_seed"], timing=1,
+                        adaptive=args.adaptive)
 
     if args.mode == "pass":
         Wm = torch.randn((p, d), dtype=torch.float64, device=dev).T
@@ -461,6 +489,8 @@ def main():
                      "bytes_per_launch": dbytes, "avg_launch_ms": dms},
         "cpu_baseline": None,
     }
+    if not args.adaptive:
+        out["adaptive"] = adaptive_leg(Xt, w, U, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Xt, dict(w, **data), sched, rep)
     if not args.no_serve:

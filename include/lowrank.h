@@ -132,7 +132,16 @@ typedef struct lr_schedule {
  *                   epoch, Cholesky-QR, Rayleigh-Ritz and the shift/gap
  *                   estimates stay FP64, so each inner solve is refined against
  *                   exactly computed residuals.  Results agree with the FP64
- *                   form to the accuracy of the solve, not bit for bit. */
+ *                   form to the accuracy of the solve, not bit for bit.
+ *   adaptive        0 (default): the q = k branch of Algorithm "main" (one
+ *                   shift-and-invert iteration with oversampling).  1: the
+ *                   adaptive partitioning of Algorithm "main" (Section 3.2):
+ *                   intervals s..q found one after another on the deflated
+ *                   matrix, by plain subspace iteration where Algorithm
+ *                   "largeDetect" finds a multiplicative gap, else by
+ *                   shift-and-invert iteration split by Algorithm
+ *                   "deltaDetect"; lr_report lists the intervals.  Dense X,
+ *                   LR_PREC_F64 and no replay only (LR_EINVAL otherwise). */
 typedef enum { LR_PREC_F64 = 0, LR_PREC_BF16_STEPS = 1 } lr_precision;
 
 typedef struct lr_options {
@@ -144,6 +153,7 @@ typedef struct lr_options {
   const lr_schedule* replay;
   int32_t timing;
   int32_t precision;      /* lr_precision */
+  int32_t adaptive;
 } lr_options;
 
 /* What a solve did.  Host struct filled by lowrank_solve. */
@@ -166,6 +176,12 @@ typedef struct lr_report {
                                      attached to that launch */
   double ms_update_probe;         /* timing = 1: same for one update kernel per epoch */
   int64_t probes;                 /* number of epochs probed */
+  /* adaptive = 1: the intervals s..q (1-based) in the order they were found,
+   * branch 0 = plain subspace iteration, 1 = shift-and-invert; cols = block
+   * width; iters = plain iterations or outer shift-and-invert iterations */
+  int32_t n_intervals;
+  int32_t interval_s[LR_MAX_P], interval_q[LR_MAX_P], interval_branch[LR_MAX_P];
+  int32_t interval_cols[LR_MAX_P], interval_iters[LR_MAX_P];
 } lr_report;
 
 typedef struct lr_plan_s* lr_plan;

@@ -42,7 +42,7 @@ lr_status fail(lr_status s, const std::string& msg) {
     if (s_ != LR_OK) return s_;     \
   } while (0)
 
-constexpr uint32_t TAG_EST_INIT = 1, TAG_SI_INIT = 2, TAG_SAMPLES = 3;
+constexpr uint32_t TAG_EST_INIT = 1, TAG_SI_INIT = 2, TAG_SAMPLES = 3, TAG_POWER_INIT = 4;
 
 inline uint32_t stream_word(uint32_t tag, uint32_t solve) { return (tag << 28) | solve; }
 
@@ -70,6 +70,12 @@ struct lr_plan_s {
   // and of the sampled products (PC x ldC)
   bool bf16_steps = false;
   int64_t ldD = 0, ldC = 0;
+  // adaptive partitioning (Algorithm "main"): the deflation basis Ud (d x ns),
+  // Z = X^T Ud (n x pad16(ns) row-major), projection temporaries, the chunk
+  // partials of the deflated inner step
+  bool adaptive = false;
+  int ns = 0;
+  double *Ud = nullptr, *Zt = nullptr, *Dw1 = nullptr, *Dw2 = nullptr, *Kd = nullptr, *Vp = nullptr;
   uint16_t *Dh = nullptr, *Dlo = nullptr, *Ch = nullptr, *Cl = nullptr;
   int k = 0, p = 0;
   double eps = 0;
@@ -144,9 +150,27 @@ struct lr_plan_s {
   }
 
   // Y = alpha X (X^T W) + beta A + gamma B   (W: d x ncols)
+  // Wout = (I - Ud Ud^T) Win for the ns directions found so far (Wout may be Win)
+  lr_status deflate(const double* Win, double* Wout, int ncols) {
+    LR_HIP(lr::gram(Ud, 1, d, ns, Win, 1, d, ncols, d, part, Kd, st));
+    LR_HIP(lr::lincomb((int64_t)ns * ncols, -1.0, Kd, 0.0, nullptr, 0.0, nullptr, Kd, st));
+    LR_HIP(lr::gemm_small(d, ns, ncols, Ud, Kd, ns, Wout, 1.0, Win, st));
+    return LR_OK;
+  }
+
+  // With directions found (ns > 0) the operator is the deflated A_{-(s-1)} = P A P.
   lr_status applyA(const double* Win, double* Yout, int ncols, double alpha = 1.0,
                    const double* A = nullptr, double beta = 0.0, const double* B = nullptr,
                    double gamma = 0.0) {
+    if (ns > 0) {
+      LR_CHECK(deflate(Win, Dw1, ncols));
+      LR_CHECK(xtw(Dw1, ncols));
+      LR_HIP(lr::pass_xt(X, T, PC, ncols, pb, 1.0, nullptr, 0.0, nullptr, 0.0, Dw2, st));
+      LR_CHECK(deflate(Dw2, Dw1, ncols));
+      LR_HIP(lr::lincomb(d * ncols, alpha, Dw1, beta, A, gamma, B, Yout, st));
+      rep.passes++;
+      return LR_OK;
+    }
     LR_CHECK(xtw(Win, ncols));
     if (sparse)
       LR_HIP(lr::csr_xt(R, T, PC, ncols, sp_part, alpha, A, beta, B, gamma, Yout, st));
@@ -210,17 +234,28 @@ struct lr_plan_s {
   // Inner solve of (lam I - XX^T) W = Srhs; the result is left in Wt.
   lr_status svrg_solve(const double* Srhs, double lam, double eta, int64_t m, int64_t b,
                        int32_t solve, double tau, int32_t fixed_epochs, int32_t* epochs_out,
-                       std::vector<double>* hist) {
+                       std::vector<double>* hist, int ncols = -1) {
     if (b > bmax) return fail(LR_EINVAL, "minibatch larger than the plan's workspace");
-    const int64_t cnt = d * p;
+    const int pc = ncols < 0 ? p : ncols;           // right-hand sides in this solve
+    const int PCn = lr::pad16(pc);                  // row stride of C
+    const int64_t cnt = d * pc;
+    lr::Deflation df;
+    if (ns > 0) {
+      df.ns = ns;
+      df.PCZ = lr::pad16(ns);
+      df.nks = lr::zbc_chunks(b);
+      df.Z = Zt;
+      df.Ud = Ud;
+      df.Vp = Vp;
+    }
     // warm start W0 = S (lam I - S^T A S)^{-1}; its gradient costs no extra pass
-    LR_CHECK(applyA(Srhs, Y, p));
-    LR_CHECK(gram_dd(Srhs, p, Y, p, H));
-    LR_HIP(lr::eigh(H, p, vals, Q, st));
-    LR_HIP(lr::shift_inverse(vals, Q, p, lam, M, st));
-    LR_HIP(lr::gemm_small(d, p, p, Srhs, M, p, Wt, 0.0, nullptr, st));
+    LR_CHECK(applyA(Srhs, Y, pc));
+    LR_CHECK(gram_dd(Srhs, pc, Y, pc, H));
+    LR_HIP(lr::eigh(H, pc, vals, Q, st));
+    LR_HIP(lr::shift_inverse(vals, Q, pc, lam, M, st));
+    LR_HIP(lr::gemm_small(d, pc, pc, Srhs, M, pc, Wt, 0.0, nullptr, st));
     LR_HIP(lr::lincomb(cnt, lam, Srhs, -1.0, Y, 0.0, nullptr, Tm1, st));
-    LR_HIP(lr::gemm_small(d, p, p, Tm1, M, p, G, -1.0, Srhs, st));
+    LR_HIP(lr::gemm_small(d, pc, pc, Tm1, M, pc, G, -1.0, Srhs, st));
     LR_HIP(lr::sumsq(Srhs, cnt, part, dnorm, st));
     LR_HIP(lr::sumsq(G, cnt, part, dnorm + 1, st));
     double nr[2];
@@ -279,8 +314,8 @@ struct lr_plan_s {
             LR_HIP(lr::step_update_bf16(X, p, b, it, Ch, Cl, ldC, PC, G, Dl, Dh, Dlo, ldD, lam,
                                         eta, st, pu));
           } else {
-            LR_HIP(lr::step_dot(X, p, b, it, scale + (t - t0) * b, Dl, C, PC, st, pd));
-            LR_HIP(lr::step_update(X, p, b, it, C, PC, G, Dl, lam, eta, st, pu));
+            LR_HIP(lr::step_dot(X, pc, b, it, scale + (t - t0) * b, Dl, C, PCn, st, pd));
+            LR_HIP(lr::step_update(X, pc, b, it, C, PCn, G, Dl, lam, eta, st, pu, df));
           }
         }
       }
@@ -289,7 +324,7 @@ struct lr_plan_s {
       rep.steps += m;
       LR_HIP(lr::lincomb(cnt, 1.0, Wt, 1.0, Dl, 0.0, nullptr, Wt, st));
       if (opt.timing) LR_HIP(hipEventRecord(ev[2], st));
-      LR_CHECK(applyA(Wt, G, p, -1.0, Wt, lam, Srhs, -1.0));
+      LR_CHECK(applyA(Wt, G, pc, -1.0, Wt, lam, Srhs, -1.0));
       if (opt.timing) LR_HIP(hipEventRecord(ev[3], st));
       LR_HIP(lr::sumsq(G, cnt, part, dnorm, st));
       LR_CHECK(read(&r, dnorm, sizeof(double)));
@@ -318,8 +353,95 @@ struct lr_plan_s {
     return LR_OK;
   }
 
+  lr_status estimate(int pc, int interval, double* theta, double* resn);
+  lr_status tune_shift(const double* theta, const double* resn, double delta, int pc,
+                       int32_t solve0, bool record, double* lam_out, double* mu_out,
+                       int* rounds_out, double* nu_out);
+  lr_status subspace_change(const double* A, const double* B, int cols, double* change);
+  lr_status power_deflated(int cols, int interval, double eps_stop, int* iters, bool* ok);
+  lr_status si_deflated(double lam, double eta, int64_t m, int64_t b, double tau,
+                        double eps_stop, int32_t first_solve, int target, int cols, int* outer,
+                        bool* ok);
+  lr_status append_basis(const double* B, int cols);
+  lr_status final_rr(const double* Sb, int cols, double* U_out, double* theta_out);
   lr_status solve(double* U_out, double* theta_out, lr_report* out_rep);
+  lr_status solve_adaptive(double* U_out, double* theta_out, lr_report* out_rep);
+  lr_status solve_intervals();
 };
+
+// Algorithm "musco" on the (deflated) A with a block of pc columns (random start
+// of stream (tag 1, interval)): est_iters plain steps, Rayleigh-Ritz, residual
+// norms.  The block is left in Sest; theta, resn: host, pc values.
+lr_status lr_plan_s::estimate(int pc, int interval, double* theta, double* resn) {
+  LR_HIP(lr::gaussian(Sest, d, pc, opt.seed, stream_word(TAG_EST_INIT, (uint32_t)interval), st));
+  if (ns > 0) LR_CHECK(deflate(Sest, Sest, pc));
+  LR_CHECK(cholqr2(Sest, Sest, pc));
+  for (int it = 0; it < opt.est_iters; ++it) {
+    LR_CHECK(applyA(Sest, Y, pc));
+    LR_CHECK(cholqr2(Y, Sest, pc));
+  }
+  LR_CHECK(applyA(Sest, Y, pc));
+  LR_CHECK(gram_dd(Sest, pc, Y, pc, H));
+  LR_HIP(lr::eigh(H, pc, vals, Q, st));
+  LR_HIP(lr::gemm_small(d, pc, pc, Y, Q, pc, Tm1, 0.0, nullptr, st));
+  LR_HIP(lr::gemm_small(d, pc, pc, Sest, Q, pc, Tm2, 0.0, nullptr, st));
+  LR_HIP(lr::residual_norms(Tm1, Tm2, vals, d, pc, res, st));
+  LR_CHECK(check_spd());
+  LR_CHECK(read(theta, vals, pc * sizeof(double)));
+  LR_CHECK(read(resn, res, pc * sizeof(double)));
+  return LR_OK;
+}
+
+// Algorithm shiftTune on the estimate block Sest (pc columns): aim
+// 1/nu_1 ~ lambda - lambda_1 into [Delta/27, Delta/5].  Inner solves use solve
+// indices solve0, solve0 + 1, ...  nu_out (may be null): the pc Ritz values of
+// the last round.
+lr_status lr_plan_s::tune_shift(const double* theta, const double* resn, double delta, int pc,
+                                int32_t solve0, bool record, double* lam_out, double* mu_out,
+                                int* rounds_out, double* nu_out) {
+  const double t1 = theta[0], r1 = resn[0];
+  double lam, mu;
+  if (opt.shift_mode == 1) {
+    lam = 1.5 * t1;
+    mu = std::max(lam - t1 - r1, delta / 30.0);
+  } else {
+    lam = t1 + r1 + delta / 10.0;
+    mu = delta / 10.0;
+  }
+  for (int r = 0; r < opt.max_shift_rounds; ++r) {
+    int64_t b, m;
+    double eta;
+    constants(t1, lam, mu, &b, &eta, &m);
+    LR_CHECK(svrg_solve(Sest, lam, eta, m, b, solve0 + r, opt.tau_shift, -1, nullptr, nullptr,
+                        pc));
+    LR_CHECK(gram_dd(Sest, pc, Wt, pc, H));
+    LR_HIP(lr::eigh(H, pc, vals, Q, st));
+    double nu[LR_MAX_P];
+    LR_CHECK(read(nu, vals, pc * sizeof(double)));
+    if (nu_out) std::memcpy(nu_out, nu, pc * sizeof(double));
+    const double nu1 = nu[0];
+    if (!(nu1 > 0)) return fail(LR_ESHIFT, "shift estimate not positive");
+    const double g = 1.0 / nu1;
+    if (record && r < LR_MAX_SHIFT_ROUNDS) {
+      rep.shift_lambda[r] = lam;
+      rep.shift_gap[r] = g;
+    }
+    *rounds_out = r + 1;
+    if (delta / 27.0 <= g && g <= delta / 5.0) {
+      *lam_out = lam;
+      *mu_out = g;
+      return LR_OK;
+    }
+    if (g > delta / 5.0) {
+      lam -= (4.0 / 9.0) * g;
+      mu = (5.0 / 9.0) * g;
+    } else {
+      lam += delta / 10.0;
+      mu = g + delta / 10.0;
+    }
+  }
+  return fail(LR_ESHIFT, "shift tuning did not reach the target interval");
+}
 
 lr_status lr_plan_s::solve(double* U_out, double* theta_out, lr_report* out_rep) {
   rep = lr_report{};
@@ -332,21 +454,7 @@ lr_status lr_plan_s::solve(double* U_out, double* theta_out, lr_report* out_rep)
   double theta[LR_MAX_P], resn[LR_MAX_P];
   if (!replay) {
     // estimate phase: subspace iteration on A with p columns, then Rayleigh-Ritz
-    LR_HIP(lr::gaussian(Sest, d, p, opt.seed, stream_word(TAG_EST_INIT, 0), st));
-    LR_CHECK(cholqr2(Sest, Sest, p));
-    for (int it = 0; it < opt.est_iters; ++it) {
-      LR_CHECK(applyA(Sest, Y, p));
-      LR_CHECK(cholqr2(Y, Sest, p));
-    }
-    LR_CHECK(applyA(Sest, Y, p));
-    LR_CHECK(gram_dd(Sest, p, Y, p, H));
-    LR_HIP(lr::eigh(H, p, vals, Q, st));
-    LR_HIP(lr::gemm_small(d, p, p, Y, Q, p, Tm1, 0.0, nullptr, st));
-    LR_HIP(lr::gemm_small(d, p, p, Sest, Q, p, Tm2, 0.0, nullptr, st));
-    LR_HIP(lr::residual_norms(Tm1, Tm2, vals, d, p, res, st));
-    LR_CHECK(check_spd());
-    LR_CHECK(read(theta, vals, p * sizeof(double)));
-    LR_CHECK(read(resn, res, p * sizeof(double)));
+    LR_CHECK(estimate(p, 0, theta, resn));
     for (int i = 0; i < p; ++i) {
       rep.theta_est[i] = theta[i];
       rep.res_est[i] = resn[i];
@@ -360,48 +468,10 @@ lr_status lr_plan_s::solve(double* U_out, double* theta_out, lr_report* out_rep)
     rep.mu_F = muF;
     const double eps_stop = eps / (k * muF);
     const double tau = std::min(1e-2, 0.1 * eps_stop);
-    // Algorithm shiftTune: aim 1/nu_1 ~ lambda - lambda_1 into [Delta/27, Delta/5]
-    const double t1 = theta[0], r1 = resn[0];
-    double lam, mu;
-    if (opt.shift_mode == 1) {
-      lam = 1.5 * t1;
-      mu = std::max(lam - t1 - r1, delta / 30.0);
-    } else {
-      lam = t1 + r1 + delta / 10.0;
-      mu = delta / 10.0;
-    }
+    const double t1 = theta[0];
+    double lam = 0, mu = 0;
     int rounds = 0;
-    bool ok = false;
-    for (int r = 0; r < opt.max_shift_rounds; ++r) {
-      int64_t b, m;
-      double eta;
-      constants(t1, lam, mu, &b, &eta, &m);
-      LR_CHECK(svrg_solve(Sest, lam, eta, m, b, r, opt.tau_shift, -1, nullptr, nullptr));
-      LR_CHECK(gram_dd(Sest, p, Wt, p, H));
-      LR_HIP(lr::eigh(H, p, vals, Q, st));
-      double nu1;
-      LR_CHECK(read(&nu1, vals, sizeof(double)));
-      if (!(nu1 > 0)) return fail(LR_ESHIFT, "shift estimate not positive");
-      const double g = 1.0 / nu1;
-      if (r < LR_MAX_SHIFT_ROUNDS) {
-        rep.shift_lambda[r] = lam;
-        rep.shift_gap[r] = g;
-      }
-      rounds = r + 1;
-      if (delta / 27.0 <= g && g <= delta / 5.0) {
-        mu = g;
-        ok = true;
-        break;
-      }
-      if (g > delta / 5.0) {
-        lam -= (4.0 / 9.0) * g;
-        mu = (5.0 / 9.0) * g;
-      } else {
-        lam += delta / 10.0;
-        mu = g + delta / 10.0;
-      }
-    }
-    if (!ok) return fail(LR_ESHIFT, "shift tuning did not reach the target interval");
+    LR_CHECK(tune_shift(theta, resn, delta, p, 0, true, &lam, &mu, &rounds, nullptr));
     rep.shift_rounds = rounds;
     sched.lambda = lam;
     sched.mu_hat = mu;
@@ -470,6 +540,224 @@ lr_status lr_plan_s::solve(double* U_out, double* theta_out, lr_report* out_rep)
   return LR_OK;
 }
 
+// sin of the largest principal angle between span(A) and span(B) (d x cols,
+// orthonormal): sqrt(1 - lambda_min((A^T B)^T (A^T B))).
+lr_status lr_plan_s::subspace_change(const double* A, const double* B, int cols, double* change) {
+  LR_HIP(lr::gram(A, 1, d, cols, B, 1, d, cols, d, part, kk1, st));
+  LR_HIP(lr::gram(kk1, 1, cols, cols, kk1, 1, cols, cols, cols, part, kk2, st));
+  LR_HIP(lr::eigh(kk2, cols, vals, Q, st));
+  double lmin;
+  LR_CHECK(read(&lmin, vals + (cols - 1), sizeof(double)));
+  *change = std::sqrt(std::max(0.0, 1.0 - lmin));
+  return LR_OK;
+}
+
+// Plain subspace iteration on the deflated A with `cols` columns and no
+// oversampling (the largeDetect branch of Algorithm "main"); the block is left
+// in S.  Stops when its span moves by at most eps_stop.
+lr_status lr_plan_s::power_deflated(int cols, int interval, double eps_stop, int* iters,
+                                    bool* ok) {
+  LR_HIP(lr::gaussian(S, d, cols, opt.seed, stream_word(TAG_POWER_INIT, (uint32_t)interval), st));
+  if (ns > 0) LR_CHECK(deflate(S, S, cols));
+  LR_CHECK(cholqr2(S, S, cols));
+  *ok = false;
+  int it = 0;
+  while (it < opt.max_outer) {
+    LR_CHECK(applyA(S, Y, cols));
+    LR_CHECK(cholqr2(Y, W, cols));
+    double ch;
+    LR_CHECK(subspace_change(S, W, cols, &ch));
+    std::swap(S, W);
+    ++it;
+    if (ch <= eps_stop) {
+      *ok = true;
+      break;
+    }
+  }
+  *iters = it;
+  return LR_OK;
+}
+
+// Shift-and-invert subspace iteration on the deflated operator with `cols`
+// columns; stops when the top-`target` Ritz subspace moves by at most
+// eps_stop.  The block is left in S.
+lr_status lr_plan_s::si_deflated(double lam, double eta, int64_t m, int64_t b, double tau,
+                                 double eps_stop, int32_t first_solve, int target, int cols,
+                                 int* outer, bool* ok) {
+  LR_HIP(lr::gaussian(S, d, cols, opt.seed, stream_word(TAG_SI_INIT, (uint32_t)first_solve), st));
+  if (ns > 0) LR_CHECK(deflate(S, S, cols));
+  LR_CHECK(cholqr2(S, S, cols));
+  *ok = false;
+  int ell = 0;
+  while (ell < opt.max_outer) {
+    int32_t e = 0;
+    LR_CHECK(svrg_solve(S, lam, eta, m, b, first_solve + ell, tau, -1, &e, nullptr, cols));
+    epochs.push_back(e);
+    LR_CHECK(gram_dd(S, cols, Wt, cols, H));
+    LR_HIP(lr::eigh(H, cols, vals, Q, st));
+    LR_HIP(lr::gemm_small(d, cols, target, S, Q, cols, V, 0.0, nullptr, st));
+    LR_CHECK(cholqr2(Wt, S, cols));
+    ++ell;
+    if (ell > 1) {
+      double ch;
+      LR_CHECK(subspace_change(Vprev, V, target, &ch));
+      rep.last_change = ch;
+      if (ch <= eps_stop) {
+        *ok = true;
+        break;
+      }
+    }
+    std::swap(V, Vprev);
+  }
+  *outer = ell;
+  return LR_OK;
+}
+
+// Append B (d x cols) to the deflation basis: Ud[:, ns:ns+cols] = CholQR2(P B);
+// then Z = X^T Ud for the deflated inner steps.
+lr_status lr_plan_s::append_basis(const double* B, int cols) {
+  if (ns + cols > p) return fail(LR_EINVAL, "deflation basis full");
+  if (ns > 0)
+    LR_CHECK(deflate(B, Tm2, cols));
+  else
+    LR_HIP(hipMemcpyAsync(Tm2, B, d * cols * sizeof(double), hipMemcpyDeviceToDevice, st));
+  LR_CHECK(cholqr2(Tm2, Ud + (int64_t)ns * d, cols));
+  ns += cols;
+  LR_HIP(lr::pass_xtw(X, Ud, ns, Zt, lr::pad16(ns), st));
+  return LR_OK;
+}
+
+// Algorithm "second stage" with C = XX^T on the orthonormal block Sb (cols
+// columns): H = (X^T Sb)^T (X^T Sb), U_k = Sb Q[:, :k], theta = top k of eig H.
+lr_status lr_plan_s::final_rr(const double* Sb, int cols, double* U_out, double* theta_out) {
+  LR_CHECK(xtw(Sb, cols));
+  LR_HIP(lr::gram(T, PC, 1, cols, T, PC, 1, cols, n, part, H, st));
+  LR_HIP(lr::eigh(H, cols, vals, Q, st));
+  double* Uo = U_out ? U_out : Tm2;
+  LR_HIP(lr::gemm_small(d, cols, k, Sb, Q, cols, Uo, 0.0, nullptr, st));
+  LR_HIP(lr::sign_fix(Uo, d, k, st));
+  double th[LR_MAX_P];
+  LR_CHECK(read(th, vals, k * sizeof(double)));
+  LR_CHECK(check_spd());
+  if (theta_out) std::memcpy(theta_out, th, k * sizeof(double));
+  return LR_OK;
+}
+
+// Algorithm "main" with adaptive partitioning (Section 3.2): intervals s..q
+// taken by plain subspace iteration on the deflated A when largeDetect finds a
+// multiplicative gap, else by shift-and-invert iteration on the deflated
+// operator, split where deltaDetect finds an additive gap.
+//
+// Readings: largeDetect returns the largest qualifying q; the estimates of
+// Algorithm "musco" on the deflated inverse are the Ritz values of the last
+// shiftTune round; the gap budget and the stopping threshold come from the
+// first interval; deflated columns are sampled with the undeflated weights.
+lr_status lr_plan_s::solve_adaptive(double* U_out, double* theta_out, lr_report* out_rep) {
+  rep = lr_report{};
+  epochs.clear();
+  sched = lr_schedule{};
+  ns = 0;
+  LR_HIP(hipMemsetAsync(dinfo, 0, sizeof(int), st));
+  LR_CHECK(prepare());
+  rep.fro2 = fro2;
+  lr_status res_ = solve_intervals();
+  const int nb = ns;
+  ns = 0;   // the final Rayleigh-Ritz and later calls see the undeflated A
+  LR_CHECK(res_ == LR_ENOCONV ? LR_OK : res_);
+  LR_CHECK(final_rr(Ud, nb, U_out, theta_out));
+  if (out_rep) *out_rep = rep;
+  if (res_ == LR_ENOCONV) return fail(LR_ENOCONV, "an iteration reached max_outer");
+  return LR_OK;
+}
+
+lr_status lr_plan_s::solve_intervals() {
+  int s0 = 0, t = 0;
+  int32_t solve_ctr = 0;
+  double delta = 0, eps_stop = 0, tau = 0;
+  bool all_ok = true;
+  while (s0 < k) {
+    const int kk = k - s0, pc = p - s0;
+    double theta[LR_MAX_P], resn[LR_MAX_P];
+    LR_CHECK(estimate(pc, t, theta, resn));
+    if (t == 0) {
+      for (int i = 0; i < p; ++i) {
+        rep.theta_est[i] = theta[i];
+        rep.res_est[i] = resn[i];
+      }
+      delta = (theta[k - 1] - theta[p - 1]) / 1.5;
+      if (!(delta > 1e-12 * theta[0])) return fail(LR_ENOGAP, "no gap between theta_k and theta_p");
+      double top = 0;
+      for (int i = 0; i < k; ++i) top += theta[i];
+      const double muF = std::sqrt(fro2 / std::max(fro2 - top, 1e-300));
+      rep.mu_F = muF;
+      eps_stop = eps / (k * muF);
+      tau = std::min(1e-2, 0.1 * eps_stop);
+      sched.delta_hat = delta;
+      sched.eps_stop = eps_stop;
+      sched.tau = tau;
+    }
+    // Algorithm largeDetect: the largest q in I \ {k} with a multiplicative gap
+    int q = -1;
+    for (int i = 0; i + 1 < kk; ++i)
+      if (theta[i + 1] <= theta[i] * (1.0 - 1.0 / ((double)p * p))) q = i;
+    int cols = 0, iters = 0, branch = 0;
+    bool ok = false;
+    if (q >= 0) {
+      cols = q + 1;
+      LR_CHECK(power_deflated(cols, t, eps_stop, &iters, &ok));
+      LR_CHECK(append_basis(S, cols));
+    } else {
+      branch = 1;
+      double lam = 0, mu = 0, nu[LR_MAX_P];
+      int rounds = 0;
+      LR_CHECK(tune_shift(theta, resn, delta, pc, solve_ctr, t == 0, &lam, &mu, &rounds, nu));
+      if (t == 0) rep.shift_rounds = rounds;
+      solve_ctr += rounds;
+      // Algorithm deltaDetect on the estimates 1/nu_i of lambda - lambda_i
+      q = kk - 1;
+      for (int i = 0; i + 1 < kk; ++i)
+        if (1.0 / nu[i + 1] - 1.0 / nu[i] >= 5.0 * delta / 9.0) {
+          q = i;
+          break;
+        }
+      cols = q == kk - 1 ? pc : q + 1;
+      int64_t b, m;
+      double eta;
+      constants(theta[0], lam, mu, &b, &eta, &m);
+      sched.lambda = lam;
+      sched.mu_hat = mu;
+      sched.eta = eta;
+      sched.m = m;
+      sched.b = b;
+      LR_CHECK(si_deflated(lam, eta, m, b, tau, eps_stop, solve_ctr, q + 1, cols, &iters, &ok));
+      solve_ctr += iters;
+      if (q < kk - 1) {   // keep the interval's own directions: top Ritz vectors in span(S)
+        LR_CHECK(applyA(S, Y, cols));
+        LR_CHECK(gram_dd(S, cols, Y, cols, H));
+        LR_HIP(lr::eigh(H, cols, vals, Q, st));
+        LR_HIP(lr::gemm_small(d, cols, q + 1, S, Q, cols, Tm1, 0.0, nullptr, st));
+        LR_CHECK(append_basis(Tm1, q + 1));
+      } else {
+        LR_CHECK(append_basis(S, cols));
+      }
+    }
+    if (t < LR_MAX_P) {
+      rep.interval_s[t] = s0 + 1;
+      rep.interval_q[t] = s0 + q + 1;
+      rep.interval_branch[t] = branch;
+      rep.interval_cols[t] = cols;
+      rep.interval_iters[t] = iters;
+    }
+    all_ok = all_ok && ok;
+    s0 += q + 1;
+    ++t;
+  }
+  rep.n_intervals = t;
+  rep.outer = (int32_t)epochs.size();
+  sched.outer = rep.outer;
+  return all_ok ? LR_OK : LR_ENOCONV;
+}
+
 size_t lr_plan_s::carve(char* base) {
   size_t off = 0;
   auto take = [&](auto** ptr, int64_t count) {
@@ -488,6 +776,10 @@ size_t lr_plan_s::carve(char* base) {
   take(&Vprev, d * k);
   for (double** b : {&Wrm, &Grm, &Dlrm}) take(b, sparse ? d * PC : 0);
   for (uint16_t** b : {&Dh, &Dlo}) take(b, bf16_steps ? ldD * PC : 0);
+  for (double** b : {&Ud, &Dw1, &Dw2}) take(b, adaptive ? d * p : 0);
+  take(&Zt, adaptive ? n * PC : 0);
+  take(&Kd, adaptive ? 64 * 64 : 0);
+  take(&Vp, adaptive ? (int64_t)lr::zbc_chunks(bmax) * 64 * 64 : 0);
   for (uint16_t** b : {&Ch, &Cl}) take(b, bf16_steps ? ldC * PC : 0);
   take(&T, n * PC);
   take(&Ypart, (int64_t)pb.nsplit * dp);
@@ -628,6 +920,10 @@ lr_status plan_check(const lr_matrix* Xm, int k, int p, double eps, const lr_opt
     if (opt->precision == LR_PREC_BF16_STEPS &&
         (Xm->layout != LR_DENSE_COLMAJOR || Xm->dtype != LR_BF16))
       return fail(LR_EINVAL, "BF16 matrix-core steps need dense BF16 X");
+    if (opt->adaptive < 0 || opt->adaptive > 1) return fail(LR_EINVAL, "adaptive must be 0 or 1");
+    if (opt->adaptive &&
+        (Xm->layout != LR_DENSE_COLMAJOR || opt->precision != LR_PREC_F64 || opt->replay))
+      return fail(LR_EINVAL, "adaptive partitioning needs dense X, FP64 precision, no replay");
     if (opt->replay) {
       const lr_schedule* r = opt->replay;
       if (r->outer < 0 || (r->outer > 0 && !r->epochs) || r->b < 1 || r->b > n || r->b > 8192 ||
@@ -652,6 +948,7 @@ void plan_shape(lr_plan_s* pl, const lr_matrix* Xm, int k, int p, const lr_optio
   pl->PC = lr::pad16(p);
   pl->pb.nsplit = pl->sparse ? 0 : lr::pass_nsplit(Xm->d, Xm->n);
   pl->bf16_steps = opt && opt->precision == LR_PREC_BF16_STEPS;
+  pl->adaptive = opt && opt->adaptive == 1;
   pl->ldD = lr::pad_to(Xm->d, 32);
   pl->ldC = lr::pad_to(pl->bmax, 32);
 }
@@ -787,6 +1084,7 @@ void lowrank_options_default(lr_options* o) {
   o->replay = nullptr;
   o->timing = 0;
   o->precision = LR_PREC_F64;
+  o->adaptive = 0;
 }
 
 lr_status lowrank_plan(lr_plan* out, const lr_matrix* Xm, int k, int p, double eps,
@@ -806,7 +1104,8 @@ lr_status lowrank_plan_bytes(const lr_matrix* X, int k, int p, const lr_options*
 lr_status lowrank_solve(lr_plan plan, double* U_out, double* theta_out, lr_report* rep) {
   if (!plan) return fail(LR_EINVAL, "null plan");
   try {
-    return plan->solve(U_out, theta_out, rep);
+    return plan->adaptive ? plan->solve_adaptive(U_out, theta_out, rep)
+                          : plan->solve(U_out, theta_out, rep);
   } catch (...) {
     return fail(LR_EDEVICE, "unexpected exception");
   }

@@ -52,10 +52,23 @@ hipError_t draw_chunk(int64_t n, const uint64_t* cdf, uint64_t seed, uint32_t t0
 hipError_t step_dot(const XView& X, int p, int64_t b, const int32_t* idx, const double* scale,
                     const double* Dl, double* C, int PC, hipStream_t st,
                     const Probe& pr = Probe());
-// Inner step, part 2: Dl <- Dl - eta (G + lam Dl - X_B C).  b <= 8192.
+// Deflation of an inner step (Section 3.1): with ns > 0 the update uses the
+// sampled columns of (I - Ud Ud^T) X.  Z = X^T Ud (n x PCZ row-major, PCZ =
+// pad16(ns)); Ud d x ns column-major (ld d); Vp scratch of nks x PCZ x PC
+// doubles, nks = zbc_chunks(b).
+struct Deflation {
+  int ns = 0, PCZ = 0, nks = 0;
+  const double* Z = nullptr;
+  const double* Ud = nullptr;
+  double* Vp = nullptr;
+};
+int zbc_chunks(int64_t b);
+// Inner step, part 2: Dl <- Dl - eta (G + lam Dl - P X_B C), P = I - Ud Ud^T
+// when deflating (else identity).  b <= 8192.
 hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, const double* C,
                        int PC, const double* G, double* Dl, double lam, double eta,
-                       hipStream_t st, const Probe& pr = Probe());
+                       hipStream_t st, const Probe& pr = Probe(),
+                       const Deflation& df = Deflation());
 // Draw only (for testing the sampler).
 hipError_t sample_only(int64_t n, const uint64_t* cdf, uint64_t seed, uint32_t step,
                        uint32_t epoch, uint32_t word3, int64_t b, int32_t* idx, double* scale,

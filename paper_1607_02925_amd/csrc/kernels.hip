@@ -570,17 +570,18 @@ __global__ __launch_bounds__(NT) void k_reduce_y(const double* __restrict__ part
 // Dl <- Dl - eta (G + lam Dl - U),  U[r, j] = sum_s X[r, idx[s]] C[s * PC + j].
 // The NW waves split the b samples (indices staged in LDS) and load G sample
 // blocks ahead.
-template <typename TX, int NW, int G, int PC, int NTW, int KS>
+template <typename TX, int NW, int G, int PC, int NTW, int KS, bool DEFL = false>
 __global__ __launch_bounds__(NW * 64) void k_step_update(const TX* __restrict__ X, int64_t ld,
                                                          int64_t d, int64_t b,
                                                          const int32_t* __restrict__ idx,
                                                          const double* __restrict__ C, int p,
                                                          const double* __restrict__ Gr,
                                                          double* __restrict__ Dl, double lam,
-                                                         double eta) {
+                                                         double eta, Deflation df) {
   __shared__ double red[NTW * 256];
   __shared__ double slots[NW * NTW * 256];
   __shared__ int sidx[KS];
+  __shared__ double vs[DEFL ? 64 * 16 * NTW : 1];
   const int t = threadIdx.x, wave = t / 64, l = t % 64;
   const int lm = l % 16, q = l / 16;
   // Workgroups go to the 8 XCDs in turn; the grid (a multiple of 8 tiles) is
@@ -637,11 +638,48 @@ __global__ __launch_bounds__(NW * 64) void k_step_update(const TX* __restrict__ 
         for (int u = 0; u < NTW; ++u) acc[u] = mfma_f64(ldx(&x[i][s], 0), nv[i][s][u], acc[u]);
   }
   waves_to_lds<NW, NTW>(red, slots, acc, q, lm);
+  if constexpr (DEFL) {
+    // deflated columns: X_B C loses its part along Ud, Ud (Z_B C), with the
+    // chunk partials of Z_B C (Z = Ud^T X) summed in chunk order
+    for (int e = t; e < df.ns * 16 * NTW; e += NW * 64) {
+      const int tq = e / (16 * NTW), j = nt0 * 16 + e % (16 * NTW);
+      double v = 0.0;
+      if (j < PC)
+        for (int ks = 0; ks < df.nks; ++ks) v += df.Vp[((int64_t)ks * df.PCZ + tq) * PC + j];
+      vs[e] = v;
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int e = t + u * NW * 64;
-    if (eval[u]) Dl[eo[u]] = e_dl[u] - eta * (e_g[u] + lam * e_dl[u] - red[e]);
+    if (!eval[u]) continue;
+    double U = red[e];
+    if constexpr (DEFL) {
+      const int64_t er = r0 + (e % 256) / 16;
+      const int jl = (e / 256) * 16 + e % 16;
+      double c = 0.0;
+      for (int tq = 0; tq < df.ns; ++tq) c += df.Ud[(int64_t)tq * d + er] * vs[tq * 16 * NTW + jl];
+      U -= c;
+    }
+    Dl[eo[u]] = e_dl[u] - eta * (e_g[u] + lam * e_dl[u] - U);
   }
+}
+
+// Chunk partials of Z_B C for a deflated inner step: Vp[ks][t][j] =
+// sum over samples s of chunk ks of Z[idx_s * PCZ + t] C[s * PC + j]
+// (Z = X^T Ud, n x PCZ row-major); one 16 x 16 tile per workgroup.
+constexpr int ZKS = 256;   // samples per chunk
+__global__ __launch_bounds__(NT) void k_zbc(const double* __restrict__ Z, int PCZ,
+                                            const int32_t* __restrict__ idx,
+                                            const double* __restrict__ C, int PC, int64_t b,
+                                            double* __restrict__ Vp) {
+  const int t = blockIdx.x * 16 + threadIdx.x / 16, j = blockIdx.y * 16 + threadIdx.x % 16;
+  const int64_t s0 = (int64_t)blockIdx.z * ZKS;
+  const int64_t s1 = min(b, s0 + ZKS);
+  double acc = 0.0;
+  for (int64_t s = s0; s < s1; ++s) acc = fma(Z[(int64_t)idx[s] * PCZ + t], C[s * PC + j], acc);
+  Vp[((int64_t)blockIdx.z * PCZ + t) * PC + j] = acc;
 }
 
 // All draws of `steps` consecutive inner steps (from step t0) of one epoch:
@@ -1243,27 +1281,41 @@ hipError_t step_dot(const XView& X, int p, int64_t b, const int32_t* idx, const 
   return launch_xtm<16, 1, 4, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
 }
 
+int zbc_chunks(int64_t b) { return (int)((b + ZKS - 1) / ZKS); }
+
 hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, const double* C,
                        int PC, const double* G, double* Dl, double lam, double eta,
-                       hipStream_t st, const Probe& pr) {
+                       hipStream_t st, const Probe& pr, const Deflation& df) {
   if (p > 64 || b > KSTAGE || pad16(p) != PC) return hipErrorInvalidValue;
+  const bool defl = df.ns > 0;
+  if (defl) {
+    if (df.ns > 64 || df.PCZ != pad16(df.ns) || !df.Z || !df.Vp || !df.Ud ||
+        df.nks != zbc_chunks(b))
+      return hipErrorInvalidValue;
+    k_zbc<<<dim3((unsigned)(df.PCZ / 16), (unsigned)(PC / 16), (unsigned)df.nks), NT, 0, st>>>(
+        df.Z, df.PCZ, idx, C, PC, b, df.Vp);
+  }
   // one 16-column slice per workgroup: twice the gathers of one slice per
   // row tile, but twice the workgroups, which this latency-bound step needs
   dim3 grid((unsigned)(((X.d + 15) / 16 + 7) / 8 * 8), (unsigned)((p + 15) / 16));
   // waves split the samples: as many as give each about one prefetch group
+#define LR_UPDATE(NWV, KSV)                                                                   \
+  LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV, {                                           \
+    if (defl)                                                                                 \
+      launch(k_step_update<TX, NWV, 4, 16 * NTV, 1, KSV, true>, grid, dim3(NWV * 64), st, pr, \
+             (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta, df);                   \
+    else                                                                                      \
+      launch(k_step_update<TX, NWV, 4, 16 * NTV, 1, KSV>, grid, dim3(NWV * 64), st, pr,       \
+             (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta, df);                   \
+  }))
   if (b <= 256) {
-    LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV,
-        launch(k_step_update<TX, 4, 4, 16 * NTV, 1, 256>, grid, dim3(256), st, pr,
-               (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta)));
+    LR_UPDATE(4, 256);
   } else if (b <= 512) {
-    LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV,
-        launch(k_step_update<TX, 8, 4, 16 * NTV, 1, 512>, grid, dim3(512), st, pr,
-               (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta)));
+    LR_UPDATE(8, 512);
   } else {
-    LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV,
-        launch(k_step_update<TX, 16, 4, 16 * NTV, 1, KSTAGE>, grid, dim3(1024), st, pr,
-               (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta)));
+    LR_UPDATE(16, KSTAGE);
   }
+#undef LR_UPDATE
   return hipGetLastError();
 }
 

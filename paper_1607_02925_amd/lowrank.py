@@ -44,7 +44,7 @@ class lr_options(ctypes.Structure):
                 ("polish", ctypes.c_int32), ("batch", ctypes.c_int64),
                 ("eta_scale", ctypes.c_double), ("tau_shift", ctypes.c_double),
                 ("replay", ctypes.POINTER(lr_schedule)), ("timing", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("adaptive", ctypes.c_int32)]
 
 
 class lr_report(ctypes.Structure):
@@ -58,7 +58,12 @@ class lr_report(ctypes.Structure):
                 ("last_change", ctypes.c_double), ("ms_pass_total", ctypes.c_double),
                 ("ms_steps_total", ctypes.c_double), ("timed_passes", ctypes.c_int64),
                 ("timed_steps", ctypes.c_int64), ("ms_sample_dot_probe", ctypes.c_double),
-                ("ms_update_probe", ctypes.c_double), ("probes", ctypes.c_int64)]
+                ("ms_update_probe", ctypes.c_double), ("probes", ctypes.c_int64),
+                ("n_intervals", ctypes.c_int32),
+                ("interval_s", ctypes.c_int32 * LR_MAX_P), ("interval_q", ctypes.c_int32 * LR_MAX_P),
+                ("interval_branch", ctypes.c_int32 * LR_MAX_P),
+                ("interval_cols", ctypes.c_int32 * LR_MAX_P),
+                ("interval_iters", ctypes.c_int32 * LR_MAX_P)]
 
 
 class lr_ticket_info(ctypes.Structure):
@@ -232,7 +237,7 @@ def _matrix(Xt):
 
 def make_options(seed=0, shift_mode=0, est_iters=4, max_outer=2000, max_epochs=60,
                  max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0, tau_shift=1e-2,
-                 replay=None, timing=0, precision=0):
+                 replay=None, timing=0, precision=0, adaptive=0):
     """lr_options plus the host objects it points to (kept alive by the caller)."""
     lib = load_library()
     opt = lr_options()
@@ -242,6 +247,7 @@ def make_options(seed=0, shift_mode=0, est_iters=4, max_outer=2000, max_epochs=6
     opt.max_epochs, opt.max_shift_rounds, opt.polish = max_epochs, max_shift_rounds, polish
     opt.batch, opt.eta_scale, opt.tau_shift, opt.timing = batch, eta_scale, tau_shift, timing
     opt.precision = precision
+    opt.adaptive = adaptive
     keep = None
     if replay is not None:
         sc, arr = replay.to_c()
@@ -267,7 +273,7 @@ class Plan:
 
     def __init__(self, Xt, k, p, eps, seed=0, shift_mode=0, est_iters=4, max_outer=2000,
                  max_epochs=60, max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0,
-                 tau_shift=1e-2, replay=None, timing=0, precision=0):
+                 tau_shift=1e-2, replay=None, timing=0, precision=0, adaptive=0):
         import torch
         self.lib = load_library()
         self._mat = _matrix(Xt)
@@ -279,7 +285,7 @@ class Plan:
             seed=seed, shift_mode=shift_mode, est_iters=est_iters, max_outer=max_outer,
             max_epochs=max_epochs, max_shift_rounds=max_shift_rounds, polish=polish, batch=batch,
             eta_scale=eta_scale, tau_shift=tau_shift, replay=replay, timing=timing,
-            precision=precision)
+            precision=precision, adaptive=adaptive)
         self._opt = opt
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -466,4 +472,8 @@ def report_dict(rep, p):
         "timed_passes": rep.timed_passes, "timed_steps": rep.timed_steps,
         "ms_sample_dot_probe": rep.ms_sample_dot_probe, "ms_update_probe": rep.ms_update_probe,
         "probes": rep.probes,
+        "intervals": [{"s": rep.interval_s[i], "q": rep.interval_q[i],
+                       "branch": "power" if rep.interval_branch[i] == 0 else "shift-invert",
+                       "cols": rep.interval_cols[i], "iters": rep.interval_iters[i]}
+                      for i in range(min(rep.n_intervals, LR_MAX_P))],
     }
