@@ -247,6 +247,26 @@ lr_status lowrank_op_cholqr2(lr_plan plan, const double* W, double* S_out, int n
 lr_status lowrank_op_eigh(lr_plan plan, const double* H, int m, double* vals_out,
                           double* vecs_out);
 
+/* Algorithm "musco" (Section 2.4) on A = XX^T with a block of ncols columns
+ * (2 <= ncols <= p): `iters` plain subspace-iteration steps from the Gaussian
+ * block of stream (tag 1, stream_index), each followed by Cholesky-QR2, then
+ * Rayleigh-Ritz (Algorithm "second stage" with C = A).
+ *   theta_out  host, ncols: Ritz values, descending
+ *   res_out    host, ncols: residual norms ||A v_i - theta_i v_i|| (may be NULL)
+ *   V_out      device, d x ncols: the Ritz vectors v_i (may be NULL) */
+lr_status lowrank_op_estimate(lr_plan plan, int ncols, int iters, int32_t stream_index,
+                              double* theta_out, double* res_out, double* V_out);
+
+/* Plain subspace iteration (Algorithm "subspace iteration", Section 2.2.1,
+ * with C = A = XX^T, no shift): S_in (device, d x ncols, full column rank) is
+ * orthonormalised by Cholesky-QR2, then at most max_iters steps
+ * S <- CholQR2(A S), stopping early once the block's span moves by at most tol
+ * in one step (tol = 0: all steps).  S_out: device, d x ncols; iters_out,
+ * change_out: host (may be NULL), steps taken and the last step's
+ * sin(largest principal angle). */
+lr_status lowrank_op_power(lr_plan plan, const double* S_in, int ncols, int max_iters,
+                           double tol, double* S_out, int32_t* iters_out, double* change_out);
+
 /* One inner solve of (lambda I - XX^T) W = S with a fixed number of epochs
  * (requires lowrank_op_prepare or a solve first).  res_out: host, epochs+1
  * residual norms ||G~||_F (may be NULL). */

@@ -1188,6 +1188,52 @@ lr_status lowrank_op_eigh(lr_plan plan, const double* H, int m, double* vals_out
   return LR_OK;
 }
 
+lr_status lowrank_op_estimate(lr_plan plan, int ncols, int iters, int32_t stream_index,
+                              double* theta_out, double* res_out, double* V_out) {
+  if (!plan || !theta_out || ncols < 2 || ncols > plan->p || iters < 0 || stream_index < 0 ||
+      stream_index >= (1 << 28))
+    return fail(LR_EINVAL, "bad argument");
+  const int32_t saved = plan->opt.est_iters;
+  plan->opt.est_iters = iters;
+  double res[LR_MAX_P];
+  LR_HIP(hipMemsetAsync(plan->dinfo, 0, sizeof(int), plan->st));
+  const lr_status s = plan->estimate(ncols, stream_index, theta_out, res);
+  plan->opt.est_iters = saved;
+  LR_CHECK(s);
+  if (res_out) std::memcpy(res_out, res, ncols * sizeof(double));
+  if (V_out)   // estimate() leaves the Ritz vectors Sest Q in Tm2
+    LR_HIP(hipMemcpyAsync(V_out, plan->Tm2, plan->d * ncols * sizeof(double),
+                          hipMemcpyDeviceToDevice, plan->st));
+  LR_HIP(hipStreamSynchronize(plan->st));
+  return LR_OK;
+}
+
+lr_status lowrank_op_power(lr_plan plan, const double* S_in, int ncols, int max_iters,
+                           double tol, double* S_out, int32_t* iters_out, double* change_out) {
+  if (!plan || !S_in || !S_out || ncols < 1 || ncols > plan->p || max_iters < 0 || !(tol >= 0))
+    return fail(LR_EINVAL, "bad argument");
+  lr_plan_s* pl = plan;
+  LR_HIP(hipMemsetAsync(pl->dinfo, 0, sizeof(int), pl->st));
+  LR_CHECK(pl->cholqr2(S_in, pl->S, ncols));
+  int it = 0;
+  double ch = -1.0;
+  while (it < max_iters) {
+    LR_CHECK(pl->applyA(pl->S, pl->Y, ncols));
+    LR_CHECK(pl->cholqr2(pl->Y, pl->W, ncols));
+    LR_CHECK(pl->subspace_change(pl->S, pl->W, ncols, &ch));
+    std::swap(pl->S, pl->W);
+    ++it;
+    if (tol > 0 && ch <= tol) break;
+  }
+  LR_CHECK(pl->check_spd());
+  LR_HIP(hipMemcpyAsync(S_out, pl->S, pl->d * ncols * sizeof(double), hipMemcpyDeviceToDevice,
+                        pl->st));
+  LR_HIP(hipStreamSynchronize(pl->st));
+  if (iters_out) *iters_out = it;
+  if (change_out) *change_out = ch;
+  return LR_OK;
+}
+
 lr_status lowrank_op_svrg_solve(lr_plan plan, const double* S, double lambda, double eta,
                                 int64_t m, int64_t b, int32_t solve, int32_t epochs,
                                 double* W_out, double* res_out) {

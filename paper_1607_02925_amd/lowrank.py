@@ -102,6 +102,12 @@ SIGNATURES = {
     "lowrank_op_gaussian": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _P]),
     "lowrank_op_cholqr2": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "lowrank_op_eigh": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P]),
+    "lowrank_op_estimate": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double), _P]),
+    "lowrank_op_power": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double, _P,
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_double)]),
     "lowrank_op_svrg_solve": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                              ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
@@ -369,6 +375,27 @@ class Plan:
         vecs = torch.empty((m, m), dtype=torch.float64, device=self.device)
         _check(self.lib.lowrank_op_eigh(self._h, _ptr(Hc), m, _ptr(vals), _ptr(vecs)))
         return vals, vecs.T
+
+    def estimate(self, ncols, iters=4, stream_index=0):
+        """Algorithm musco on A with ncols columns: (theta, residual norms, V d x ncols)."""
+        import torch
+        th = (ctypes.c_double * ncols)()
+        rs = (ctypes.c_double * ncols)()
+        V = torch.empty((ncols, self.d), dtype=torch.float64, device=self.device)
+        _check(self.lib.lowrank_op_estimate(self._h, ncols, iters, stream_index, th, rs, _ptr(V)))
+        return np.array(th[:]), np.array(rs[:]), V.T
+
+    def power(self, S, max_iters, tol=0.0):
+        """Plain subspace iteration on A from S (d x ncols): (S_out, iters, change)."""
+        import torch
+        Sc = S.T.contiguous()
+        out = torch.empty_like(Sc)
+        it = ctypes.c_int32()
+        ch = ctypes.c_double()
+        _check(self.lib.lowrank_op_power(self._h, _ptr(Sc), Sc.shape[0], int(max_iters),
+                                         float(tol), _ptr(out), ctypes.byref(it),
+                                         ctypes.byref(ch)))
+        return out.T, it.value, ch.value
 
     def svrg_solve(self, S, lam, eta, m, b, solve, epochs):
         import torch
