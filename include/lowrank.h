@@ -141,7 +141,12 @@ typedef struct lr_schedule {
  *                   "largeDetect" finds a multiplicative gap, else by
  *                   shift-and-invert iteration split by Algorithm
  *                   "deltaDetect"; lr_report lists the intervals.  Dense X,
- *                   LR_PREC_F64 and no replay only (LR_EINVAL otherwise). */
+ *                   LR_PREC_F64 and no replay only (LR_EINVAL otherwise).
+ *   norm            the norm xi of the guarantee ||X - Pi X||_xi <= (1 + eps)
+ *                   ||X - X_k||_xi (Corollary "mainResult"): 0 Frobenius
+ *                   (default), 1 spectral.  eps is rescaled by mu, a rough
+ *                   bound on ||X||_xi / ||X - X_k||_xi from the estimate
+ *                   phase (lr_report.mu_F holds the mu used). */
 typedef enum { LR_PREC_F64 = 0, LR_PREC_BF16_STEPS = 1 } lr_precision;
 
 typedef struct lr_options {
@@ -154,6 +159,7 @@ typedef struct lr_options {
   int32_t timing;
   int32_t precision;      /* lr_precision */
   int32_t adaptive;
+  int32_t norm;
 } lr_options;
 
 /* What a solve did.  Host struct filled by lowrank_solve. */
@@ -161,7 +167,9 @@ typedef struct lr_report {
   double theta_est[LR_MAX_P];     /* estimate-phase Ritz values of XX^T, descending */
   double res_est[LR_MAX_P];       /* their residual norms ||A s_i - theta_i s_i|| */
   double fro2;                    /* ||X||_F^2 */
-  double mu_F;                    /* ||X||_F / sqrt(||X||_F^2 - sum_{i<=k} theta_i) */
+  double mu_F;                    /* the eps rescaling mu: ||X||_F / sqrt(||X||_F^2 -
+                                     sum_{i<=k} theta_i), or sqrt(theta_1 / theta_{k+1})
+                                     for the spectral norm */
   int32_t shift_rounds;
   double shift_lambda[LR_MAX_SHIFT_ROUNDS];   /* lambda tried in each round */
   double shift_gap[LR_MAX_SHIFT_ROUNDS];      /* its estimate 1/nu_1 of lambda - lambda_1 */

@@ -50,7 +50,7 @@ from .sampling import column_sq_norms, build_table
 from .linalg import cholqr2, eigh_desc, sign_fix
 from .lowrank import (LR_OK, LR_ENOCONV, LR_ENOGAP, LR_EINVAL, LowRankError, Options, Schedule,
                       decode, deflate, apply_A, solver_constants, svrg_solve, tune_shift,
-                      final_rr, validate)
+                      final_rr, validate, stop_scale)
 
 TAG_POWER_INIT = 4
 
@@ -181,8 +181,7 @@ def solve_adaptive(xt, storage, k, p, eps, opt=None):
             delta = (theta[k - 1] - theta[p - 1]) / 1.5
             if not delta > 1e-12 * theta[0]:
                 raise LowRankError(LR_ENOGAP, "no gap between theta_k and theta_p")
-            tail = max(fro2 - float(np.sum(theta[:k])), 1e-300)
-            eps_stop = eps / (k * math.sqrt(fro2 / tail))
+            eps_stop = eps / (k * stop_scale(theta, fro2, k, opt.norm))
             tau = min(1e-2, 0.1 * eps_stop)
         q = large_detect(theta[:kk], p)
         if q >= 0:

@@ -63,6 +63,7 @@ class Options:
     batch: int = 0                  # 0 = automatic
     eta_scale: float = 1.0
     tau_shift: float = 1e-2
+    norm: str = "fro"               # "fro" or "spectral": the norm of the (1 + eps) guarantee
 
 
 @dataclass
@@ -297,6 +298,19 @@ class Result:
     changes: list = None
 
 
+def stop_scale(theta, fro2, k, norm="fro"):
+    """The rough upper bound mu on ||X|| / ||X - X_k|| by which eps is rescaled
+    (Corollary "mainResult"; Algorithm "main", first line), from the estimate
+    phase: Frobenius ||X||_F / sqrt(||X||_F^2 - sum_{i<=k} theta_i), spectral
+    sqrt(theta_1 / theta_{k+1})."""
+    if norm == "spectral":
+        return math.sqrt(theta[0] / max(theta[k], 1e-300))
+    if norm != "fro":
+        raise LowRankError(LR_EINVAL, "norm must be fro or spectral")
+    tail = max(fro2 - float(np.sum(theta[:k])), 1e-300)
+    return math.sqrt(fro2 / tail)
+
+
 def validate(d, n, k, p):
     if not (1 <= k < p < d) or p > n:
         raise LowRankError(LR_EINVAL, "need 1 <= k < p < d and p <= n")
@@ -319,8 +333,7 @@ def solve(xt, storage, k, p, eps, opt=None, replay=None):
     delta = (theta[k - 1] - theta[p - 1]) / 1.5
     if not delta > 1e-12 * theta[0]:
         raise LowRankError(LR_ENOGAP, "no gap between theta_k and theta_p")
-    tail = max(fro2 - float(np.sum(theta[:k])), 1e-300)
-    mu_F = math.sqrt(fro2 / tail)
+    mu_F = stop_scale(theta, fro2, k, opt.norm)
     eps_stop = eps / (k * mu_F)
     tau = min(1e-2, 0.1 * eps_stop)
     if replay is None:

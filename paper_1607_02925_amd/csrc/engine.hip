@@ -354,6 +354,15 @@ struct lr_plan_s {
   }
 
   lr_status estimate(int pc, int interval, double* theta, double* resn);
+  // The rough upper bound mu on ||X|| / ||X - X_k|| by which eps is rescaled
+  // (Corollary "mainResult"), from the estimate-phase Ritz values: Frobenius
+  // ||X||_F / sqrt(||X||_F^2 - sum_{i<=k} theta_i), spectral sqrt(theta_1 / theta_{k+1}).
+  double stop_scale(const double* theta) const {
+    if (opt.norm == 1) return std::sqrt(theta[0] / std::max(theta[k], 1e-300));
+    double top = 0;
+    for (int i = 0; i < k; ++i) top += theta[i];
+    return std::sqrt(fro2 / std::max(fro2 - top, 1e-300));
+  }
   lr_status tune_shift(const double* theta, const double* resn, double delta, int pc,
                        int32_t solve0, bool record, double* lam_out, double* mu_out,
                        int* rounds_out, double* nu_out);
@@ -461,10 +470,7 @@ lr_status lr_plan_s::solve(double* U_out, double* theta_out, lr_report* out_rep)
     }
     const double delta = (theta[k - 1] - theta[p - 1]) / 1.5;
     if (!(delta > 1e-12 * theta[0])) return fail(LR_ENOGAP, "no gap between theta_k and theta_p");
-    double top = 0;
-    for (int i = 0; i < k; ++i) top += theta[i];
-    const double tail = std::max(fro2 - top, 1e-300);
-    const double muF = std::sqrt(fro2 / tail);
+    const double muF = stop_scale(theta);
     rep.mu_F = muF;
     const double eps_stop = eps / (k * muF);
     const double tau = std::min(1e-2, 0.1 * eps_stop);
@@ -686,9 +692,7 @@ lr_status lr_plan_s::solve_intervals() {
       }
       delta = (theta[k - 1] - theta[p - 1]) / 1.5;
       if (!(delta > 1e-12 * theta[0])) return fail(LR_ENOGAP, "no gap between theta_k and theta_p");
-      double top = 0;
-      for (int i = 0; i < k; ++i) top += theta[i];
-      const double muF = std::sqrt(fro2 / std::max(fro2 - top, 1e-300));
+      const double muF = stop_scale(theta);
       rep.mu_F = muF;
       eps_stop = eps / (k * muF);
       tau = std::min(1e-2, 0.1 * eps_stop);
@@ -921,6 +925,7 @@ lr_status plan_check(const lr_matrix* Xm, int k, int p, double eps, const lr_opt
         (Xm->layout != LR_DENSE_COLMAJOR || Xm->dtype != LR_BF16))
       return fail(LR_EINVAL, "BF16 matrix-core steps need dense BF16 X");
     if (opt->adaptive < 0 || opt->adaptive > 1) return fail(LR_EINVAL, "adaptive must be 0 or 1");
+    if (opt->norm < 0 || opt->norm > 1) return fail(LR_EINVAL, "norm must be 0 or 1");
     if (opt->adaptive &&
         (Xm->layout != LR_DENSE_COLMAJOR || opt->precision != LR_PREC_F64 || opt->replay))
       return fail(LR_EINVAL, "adaptive partitioning needs dense X, FP64 precision, no replay");
@@ -1085,6 +1090,7 @@ void lowrank_options_default(lr_options* o) {
   o->timing = 0;
   o->precision = LR_PREC_F64;
   o->adaptive = 0;
+  o->norm = 0;
 }
 
 lr_status lowrank_plan(lr_plan* out, const lr_matrix* Xm, int k, int p, double eps,

@@ -44,7 +44,8 @@ class lr_options(ctypes.Structure):
                 ("polish", ctypes.c_int32), ("batch", ctypes.c_int64),
                 ("eta_scale", ctypes.c_double), ("tau_shift", ctypes.c_double),
                 ("replay", ctypes.POINTER(lr_schedule)), ("timing", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("adaptive", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("adaptive", ctypes.c_int32),
+                ("norm", ctypes.c_int32)]
 
 
 class lr_report(ctypes.Structure):
@@ -243,7 +244,7 @@ def _matrix(Xt):
 
 def make_options(seed=0, shift_mode=0, est_iters=4, max_outer=2000, max_epochs=60,
                  max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0, tau_shift=1e-2,
-                 replay=None, timing=0, precision=0, adaptive=0):
+                 replay=None, timing=0, precision=0, adaptive=0, norm=0):
     """lr_options plus the host objects it points to (kept alive by the caller)."""
     lib = load_library()
     opt = lr_options()
@@ -254,6 +255,7 @@ def make_options(seed=0, shift_mode=0, est_iters=4, max_outer=2000, max_epochs=6
     opt.batch, opt.eta_scale, opt.tau_shift, opt.timing = batch, eta_scale, tau_shift, timing
     opt.precision = precision
     opt.adaptive = adaptive
+    opt.norm = norm
     keep = None
     if replay is not None:
         sc, arr = replay.to_c()
@@ -279,7 +281,7 @@ class Plan:
 
     def __init__(self, Xt, k, p, eps, seed=0, shift_mode=0, est_iters=4, max_outer=2000,
                  max_epochs=60, max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0,
-                 tau_shift=1e-2, replay=None, timing=0, precision=0, adaptive=0):
+                 tau_shift=1e-2, replay=None, timing=0, precision=0, adaptive=0, norm=0):
         import torch
         self.lib = load_library()
         self._mat = _matrix(Xt)
@@ -291,7 +293,7 @@ class Plan:
             seed=seed, shift_mode=shift_mode, est_iters=est_iters, max_outer=max_outer,
             max_epochs=max_epochs, max_shift_rounds=max_shift_rounds, polish=polish, batch=batch,
             eta_scale=eta_scale, tau_shift=tau_shift, replay=replay, timing=timing,
-            precision=precision, adaptive=adaptive)
+            precision=precision, adaptive=adaptive, norm=norm)
         self._opt = opt
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -62,3 +62,21 @@ def test_adaptive_option_checks(torch_cuda):
     with pytest.raises(lowrank.LowRankError) as e:
         lowrank.Plan(to_dev(torch_cuda, xt, "bf16"), 2, 6, 1e-4, adaptive=1, precision=1)
     assert e.value.code == lowrank.LR_EINVAL
+
+
+@pytest.mark.parametrize("name,adaptive", [("planted-256x2048-f64", 0),
+                                           ("planted-256x8192-f32", 1)])
+def test_spectral_norm_option(torch_cuda, name, adaptive):
+    """norm = 1 rescales eps by sqrt(theta_1 / theta_{k+1}); the GPU takes the
+    oracle's decisions and reaches its subspace."""
+    from paper_1607_02925_amd import lowrank
+    w = workloads.workload(name)
+    opt = oracle.Options(seed=w["solver_seed"], norm="spectral")
+    fn = oracle.solve_adaptive if adaptive else oracle.solve
+    ref = fn(w["Xt"], w["storage"], w["k"], w["p"], w["eps"], opt)
+    plan = lowrank.Plan(to_dev(torch_cuda, w["Xt"], w["storage"]), w["k"], w["p"], w["eps"],
+                        seed=w["solver_seed"], adaptive=adaptive, norm=1)
+    st, U, theta, rep = plan.solve()
+    assert st == ref.status == 0
+    assert sin_theta(ref.U, U.cpu().numpy()) <= 1e-6
+    np.testing.assert_allclose(theta, ref.theta, rtol=1e-9)

@@ -2,6 +2,7 @@
 largeDetect / deltaDetect and deflation) against the rules as the paper states
 them and against the exact SVD."""
 import numpy as np
+import pytest
 
 import oracle
 import workloads
@@ -89,3 +90,24 @@ def test_adaptive_clustered_spectrum_is_one_interval():
     uk, s = _exact(data["Xt"].T, k)
     assert oracle.sin_theta(uk, r.U) <= eps / k
     np.testing.assert_allclose(r.theta, s[:k] ** 2, rtol=1e-10)
+
+
+def test_spectral_norm_guarantee():
+    """Corollary "mainResult" for the spectral norm: with eps rescaled by
+    mu_2 = sqrt(theta_1 / theta_{k+1}), ||X - U U^T X||_2 <= (1 + eps) sigma_{k+1}
+    (the exact rank-k error), checked with LAPACK's SVD; both the q = k branch
+    and the adaptive loop."""
+    d, n, k, p, eps = 160, 2500, 6, 12, 1e-3
+    i = np.arange(1, d + 1, dtype=float)
+    sig = np.where(i <= k, 1.0 + 0.02 * (k - i), 0.8 * i ** -0.5)
+    data = workloads.planted_dense(d, n, sig, 21, "f64")
+    X = data["Xt"].T
+    s = np.linalg.svd(X, compute_uv=False)
+    for fn in (oracle.solve, oracle.solve_adaptive):
+        r = fn(data["Xt"], "f64", k, p, eps, oracle.Options(seed=4, norm="spectral"))
+        assert r.status == 0
+        R = X - r.U @ (r.U.T @ X)
+        assert np.linalg.norm(R, 2) <= (1 + eps) * s[k]
+    th = oracle.estimate_phase(X, k, p, 4, 4)[1]
+    assert oracle.lowrank.stop_scale(th, float(np.sum(X * X)), k, "spectral") == \
+        pytest.approx(np.sqrt(th[0] / th[k]))
