@@ -26,7 +26,12 @@ def test_op_estimate(case, ncols, iters, stream):
     S, tho, rso = oracle.estimate_deflated(X, np.zeros((X.shape[0], 0)), ncols,
                                            w["solver_seed"], stream, iters)
     np.testing.assert_allclose(th, tho, rtol=1e-10)
-    assert np.max(np.abs(rs - rso)) <= 1e-10 * tho[0]
+    # the block residual ||A S - S H||_F does not depend on the rotation of the
+    # Ritz vectors inside the block; the per-vector residuals do, and that
+    # rotation is undetermined where Ritz values coincide (sigma_1..4 = 1 here)
+    assert abs(np.linalg.norm(rs) - np.linalg.norm(rso)) <= 1e-10 * tho[0]
+    if np.min(np.abs(np.diff(tho))) > 1e-6 * tho[0]:
+        assert np.max(np.abs(rs - rso)) <= 1e-10 * tho[0]
     Vg = V.cpu().numpy()
     assert sin_theta(S, Vg) <= 1e-10
     assert np.linalg.norm(Vg.T @ Vg - np.eye(ncols)) <= 1e-12
