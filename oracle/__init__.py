@@ -21,3 +21,5 @@ from .adaptive import (  # noqa: F401
     solve_adaptive, large_detect, delta_detect, estimate_deflated, power_deflated, si_deflated,
 )
 from .lowrank import deflate  # noqa: F401
+from .lowrank import inner_schedule, inner_solve  # noqa: F401
+from .accel import accel_constants, acc_svrg_solve  # noqa: F401

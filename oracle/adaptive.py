@@ -50,7 +50,7 @@ from .sampling import column_sq_norms, build_table
 from .linalg import cholqr2, eigh_desc, sign_fix
 from .lowrank import (LR_OK, LR_ENOCONV, LR_ENOGAP, LR_EINVAL, LowRankError, Options, Schedule,
                       decode, deflate, apply_A, solver_constants, svrg_solve, tune_shift,
-                      final_rr, validate, stop_scale)
+                      final_rr, validate, stop_scale, inner_schedule, inner_solve)
 
 TAG_POWER_INIT = 4
 
@@ -115,8 +115,8 @@ def si_deflated(X, qc, Ud, sched, target, cols, seed, max_outer, max_epochs):
     epochs, changes = [], []
     V_prev = None
     for ell in range(max_outer):
-        W, e, _ = svrg_solve(X, qc, S, sched.lam, sched.eta, sched.m, sched.b, sched.tau, seed,
-                             sched.first_solve + ell, max_epochs, Ud=Ud)
+        W, e, _ = inner_solve(X, qc, S, sched, sched.tau, seed, sched.first_solve + ell,
+                              max_epochs, Ud=Ud)
         epochs.append(e)
         K = S.T @ W
         _, Q = eigh_desc(0.5 * (K + K.T))
@@ -195,9 +195,10 @@ def solve_adaptive(xt, storage, k, p, eps, opt=None):
             solve_ctr += rounds
             q = delta_detect(1.0 / out["nu"][:kk], delta)
             cols = pc if q == kk - 1 else q + 1
-            b, eta, m = solver_constants(fro2, theta[0], lam, mu, n, opt.batch, opt.eta_scale)
-            sched = Schedule(lam=lam, mu_hat=mu, delta_hat=delta, eta=eta, m=m, b=b, tau=tau,
-                             eps_stop=eps_stop, first_solve=solve_ctr)
+            sched = inner_schedule(fro2, theta[0], lam, mu, n, opt)
+            sched.delta_hat, sched.tau, sched.eps_stop = delta, tau, eps_stop
+            sched.first_solve = solve_ctr
+            b, eta, m = sched.b, sched.eta, sched.m
             B, epochs, _, ok = si_deflated(X, qc, Ud, sched, q + 1, cols, opt.seed,
                                            opt.max_outer, opt.max_epochs)
             solve_ctr += len(epochs)

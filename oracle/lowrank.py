@@ -64,6 +64,7 @@ class Options:
     eta_scale: float = 1.0
     tau_shift: float = 1e-2
     norm: str = "fro"               # "fro" or "spectral": the norm of the (1 + eps) guarantee
+    accel: bool = False             # accelerated inner solver (oracle.accel)
 
 
 @dataclass
@@ -79,6 +80,9 @@ class Schedule:
     first_solve: int = 0
     outer: int = 0
     epochs: list = field(default_factory=list)
+    accel: bool = False
+    kappa: float = 0.0
+    beta: float = 0.0
 
 
 def decode(xt, storage):
@@ -204,6 +208,30 @@ def svrg_solve(X, qc, S, lam, eta, m, b, tau, seed, solve, max_epochs,
     return Wt, e, res
 
 
+def inner_schedule(fro2, theta1, lam, mu, n, opt):
+    """The inner solver's constants for shift lam and strong-convexity
+    estimate mu: plain SVRG (solver_constants) or, with opt.accel, the
+    accelerated loop (oracle.accel)."""
+    if opt.accel:
+        from .accel import accel_constants
+        kappa, beta, b, eta, m = accel_constants(fro2, theta1, lam, mu, n, opt.batch,
+                                                 opt.eta_scale)
+        return Schedule(lam=lam, mu_hat=mu, eta=eta, m=m, b=b, accel=True, kappa=kappa,
+                        beta=beta)
+    b, eta, m = solver_constants(fro2, theta1, lam, mu, n, opt.batch, opt.eta_scale)
+    return Schedule(lam=lam, mu_hat=mu, eta=eta, m=m, b=b)
+
+
+def inner_solve(X, qc, S, sched, tau, seed, solve, max_epochs, fixed_epochs=None, Ud=None):
+    """(lam I - A) W = S by the solver the schedule names."""
+    if sched.accel:
+        from .accel import acc_svrg_solve
+        return acc_svrg_solve(X, qc, S, sched.lam, sched.kappa, sched.beta, sched.eta, sched.m,
+                              sched.b, tau, seed, solve, max_epochs, fixed_epochs, Ud)
+    return svrg_solve(X, qc, S, sched.lam, sched.eta, sched.m, sched.b, tau, seed, solve,
+                      max_epochs, fixed_epochs, Ud)
+
+
 def tune_shift(X, qc, S_est, theta, res, delta, fro2, seed, opt, n, Ud=None, solve0=0,
                out=None):
     """Alg. shiftTune on the estimate-phase block.  Returns (lam, mu_hat,
@@ -218,9 +246,9 @@ def tune_shift(X, qc, S_est, theta, res, delta, fro2, seed, opt, n, Ud=None, sol
         mu = delta / 10.0
     hist = []
     for r in range(opt.max_shift_rounds):
-        b, eta, m = solver_constants(fro2, t1, lam, mu, n, opt.batch, opt.eta_scale)
-        W, _, _ = svrg_solve(X, qc, S_est, lam, eta, m, b, opt.tau_shift, seed, solve0 + r,
-                             opt.max_epochs, Ud=Ud)
+        sched = inner_schedule(fro2, t1, lam, mu, n, opt)
+        W, _, _ = inner_solve(X, qc, S_est, sched, opt.tau_shift, seed, solve0 + r,
+                              opt.max_epochs, Ud=Ud)
         K = S_est.T @ W
         nu = eigh_desc(0.5 * (K + K.T))[0]
         if out is not None:
@@ -256,8 +284,8 @@ def si_iterate(X, qc, sched, k, p, seed, max_outer, max_epochs, replay=False, so
         solve = sched.first_solve + ell
         fixed = sched.epochs[ell] if replay else None
         if solver is None:
-            W, e, _ = svrg_solve(X, qc, S, sched.lam, sched.eta, sched.m, sched.b, sched.tau,
-                                 seed, solve, max_epochs, fixed_epochs=fixed)
+            W, e, _ = inner_solve(X, qc, S, sched, sched.tau, seed, solve, max_epochs,
+                                  fixed_epochs=fixed)
         else:
             W, e = solver(S, solve, fixed)
         epochs.append(e)
@@ -339,9 +367,8 @@ def solve(xt, storage, k, p, eps, opt=None, replay=None):
     if replay is None:
         lam, mu, rounds, hist = tune_shift(X, qc, S_est, theta, res, delta, fro2, opt.seed,
                                            opt, n)
-        b, eta, m = solver_constants(fro2, theta[0], lam, mu, n, opt.batch, opt.eta_scale)
-        sched = Schedule(lam=lam, mu_hat=mu, delta_hat=delta, eta=eta, m=m, b=b, tau=tau,
-                         eps_stop=eps_stop, first_solve=rounds)
+        sched = inner_schedule(fro2, theta[0], lam, mu, n, opt)
+        sched.delta_hat, sched.tau, sched.eps_stop, sched.first_solve = delta, tau, eps_stop, rounds
     else:
         rounds, hist = replay.first_solve, []
         sched = Schedule(lam=replay.lam, mu_hat=replay.mu_hat, delta_hat=delta,
