@@ -146,7 +146,16 @@ typedef struct lr_schedule {
  *                   ||X - X_k||_xi (Corollary "mainResult"): 0 Frobenius
  *                   (default), 1 spectral.  eps is rescaled by mu, a rough
  *                   bound on ||X||_xi / ||X - X_k||_xi from the estimate
- *                   phase (lr_report.mu_F holds the mu used). */
+ *                   phase (lr_report.mu_F holds the mu used).
+ *   accel           1: accelerated inner solver (the accelerated variant the
+ *                   paper cites with Theorem "svrgSolve"): an outer
+ *                   proximal-point loop, each step one SVRG epoch on
+ *                   ((lambda + kappa) I - XX^T) W = S + kappa Y from the last
+ *                   iterate, Y extrapolated with momentum beta; kappa and beta
+ *                   are reported in lr_report.  An outer step counts as
+ *                   an epoch; a solve may take max_epochs ceil(1 / sqrt(q))
+ *                   of them, q = mu / (mu + kappa).  0 (default): plain SVRG
+ *                   epochs.  Not with a replay schedule. */
 typedef enum { LR_PREC_F64 = 0, LR_PREC_BF16_STEPS = 1 } lr_precision;
 
 typedef struct lr_options {
@@ -160,6 +169,7 @@ typedef struct lr_options {
   int32_t precision;      /* lr_precision */
   int32_t adaptive;
   int32_t norm;
+  int32_t accel;
 } lr_options;
 
 /* What a solve did.  Host struct filled by lowrank_solve. */
@@ -190,6 +200,7 @@ typedef struct lr_report {
   int32_t n_intervals;
   int32_t interval_s[LR_MAX_P], interval_q[LR_MAX_P], interval_branch[LR_MAX_P];
   int32_t interval_cols[LR_MAX_P], interval_iters[LR_MAX_P];
+  double accel_kappa, accel_beta; /* accel = 1: kappa and beta of the last solve's schedule */
 } lr_report;
 
 typedef struct lr_plan_s* lr_plan;
@@ -281,6 +292,17 @@ lr_status lowrank_op_power(lr_plan plan, const double* S_in, int ncols, int max_
 lr_status lowrank_op_svrg_solve(lr_plan plan, const double* S, double lambda, double eta,
                                 int64_t m, int64_t b, int32_t solve, int32_t epochs,
                                 double* W_out, double* res_out);
+
+/* One accelerated inner solve of (lambda I - XX^T) W = S (the proximal-point
+ * loop of lr_options.accel; the plan must have been made with accel = 1) with a
+ * fixed number of outer steps, each one epoch of m minibatch steps of size b
+ * and step size eta at the shift lambda + kappa, followed by extrapolation
+ * with momentum beta.  kappa = 0 gives the plain solver.  res_out: host,
+ * epochs+1 residual norms ||S - (lambda I - XX^T) W||_F of the original system
+ * (may be NULL); W_out: device, d x p. */
+lr_status lowrank_op_acc_svrg_solve(lr_plan plan, const double* S, double lambda, double kappa,
+                                    double beta, double eta, int64_t m, int64_t b, int32_t solve,
+                                    int32_t epochs, double* W_out, double* res_out);
 
 
 /* ---- Request server: continuous batching of independent problems ----

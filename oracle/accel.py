@@ -23,6 +23,10 @@ acceleration of a linearly convergent solver by an outer proximal-point loop:
 The next epoch's starting gradient follows from the last one without a pass:
 G <- G - kappa (Y_k - Y_{k-1}).  Epoch e of the solve uses sample stream
 (solve, epoch e), as the plain solver does.
+
+Budget: an outer step gains a factor of about 1 - sqrt(q) where a plain epoch
+gains a constant factor, so the solve may take max_epochs * ceil(1 / sqrt(q))
+outer steps, 1 / sqrt(q) = (1 + beta) / (1 - beta).
 """
 import math
 
@@ -60,12 +64,13 @@ def acc_svrg_solve(X, qc, S, lam, kappa, beta, eta, m, b, tau, seed, solve, max_
     Yk = W.copy()
     Wprev = W.copy()
     G = G0 + kappa * W - kappa * Yk                  # inner gradient at W for S + kappa Y_0
+    budget = max_epochs * math.ceil((1.0 + beta) / (1.0 - beta))
     e = 0
     while True:
         if fixed_epochs is None:
             if res[-1] <= tau * sn:
                 break
-            if e >= max_epochs:
+            if e >= budget:
                 raise LowRankError(LR_ENOCONV, "inner solver did not converge")
         elif e >= fixed_epochs:
             break

@@ -74,6 +74,11 @@ struct lr_plan_s {
   // Z = X^T Ud (n x pad16(ns) row-major), projection temporaries, the chunk
   // partials of the deflated inner step
   bool adaptive = false;
+  // accelerated inner solver: the next iterate, two momentum points, the shifted
+  // right-hand side S + kappa Y
+  bool accel = false;
+  double acc_kappa = 0.0, acc_beta = 0.0;   // of the shift-and-invert solves
+  double *Wn = nullptr, *Ya = nullptr, *Yb = nullptr, *Racc = nullptr;
   int ns = 0;
   double *Ud = nullptr, *Zt = nullptr, *Dw1 = nullptr, *Dw2 = nullptr, *Kd = nullptr, *Vp = nullptr;
   uint16_t *Dh = nullptr, *Dlo = nullptr, *Ch = nullptr, *Cl = nullptr;
@@ -231,10 +236,33 @@ struct lr_plan_s {
     *b = bb;
   }
 
+  // Constants of the inner solver for shift lam and strong-convexity estimate
+  // mu.  Accelerated (opt.accel): kappa = max(0, sqrt(8 ||X||_F^2 theta_1 / n) - mu),
+  // beta = (1 - sqrt(q)) / (1 + sqrt(q)) with q = mu / (mu + kappa), and the plain
+  // constants taken at lam + kappa, mu + kappa.
+  struct Inner {
+    int64_t b = 0, m = 0;
+    double eta = 0, kappa = 0, beta = 0;
+  };
+  Inner inner_constants(double theta1, double lam, double mu) const {
+    Inner c;
+    if (accel) {
+      c.kappa = std::max(0.0, std::sqrt(8.0 * fro2 * theta1 / (double)n) - mu);
+      const double q = mu / (mu + c.kappa);
+      c.beta = (1.0 - std::sqrt(q)) / (1.0 + std::sqrt(q));
+    }
+    constants(theta1, lam + c.kappa, mu + c.kappa, &c.b, &c.eta, &c.m);
+    return c;
+  }
+
   // Inner solve of (lam I - XX^T) W = Srhs; the result is left in Wt.
+  // kappa > 0 or accel: the accelerated proximal-point loop, one SVRG epoch on
+  // ((lam + kappa) I - XX^T) W = Srhs + kappa Y per outer step, started at the
+  // previous iterate; the residual is that of the original system.
   lr_status svrg_solve(const double* Srhs, double lam, double eta, int64_t m, int64_t b,
                        int32_t solve, double tau, int32_t fixed_epochs, int32_t* epochs_out,
-                       std::vector<double>* hist, int ncols = -1) {
+                       std::vector<double>* hist, int ncols = -1, double kappa = 0.0,
+                       double beta = 0.0) {
     if (b > bmax) return fail(LR_EINVAL, "minibatch larger than the plan's workspace");
     const int pc = ncols < 0 ? p : ncols;           // right-hand sides in this solve
     const int PCn = lr::pad16(pc);                  // row stride of C
@@ -265,15 +293,25 @@ struct lr_plan_s {
     double r = r0;
     if (hist) hist->push_back(r);
     const uint32_t w3 = stream_word(TAG_SAMPLES, (uint32_t)solve);
+    const double lam_in = lam + kappa;   // the steps' shift
+    double* Yk = Ya;
+    double* Ynew = Yb;
+    if (accel)   // Y_0 = W_0; the inner gradient at W_0 equals the original one
+      LR_HIP(hipMemcpyAsync(Yk, Wt, cnt * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (bf16_steps) {   // sample slots beyond b stay zero for the whole solve
       LR_HIP(hipMemsetAsync(Ch, 0, ldC * PC * sizeof(uint16_t), st));
       LR_HIP(hipMemsetAsync(Cl, 0, ldC * PC * sizeof(uint16_t), st));
     }
+    // an accelerated outer step gains about 1 - sqrt(q) where a plain epoch gains a
+    // constant factor: its budget is max_epochs ceil(1 / sqrt(q)), 1 / sqrt(q) = (1 + beta) / (1 - beta)
+    const int64_t budget =
+        accel ? (int64_t)opt.max_epochs * (int64_t)std::ceil((1.0 + beta) / (1.0 - beta))
+              : (int64_t)opt.max_epochs;
     int32_t e = 0;
     for (;;) {
       if (fixed_epochs < 0) {
         if (r <= tau * sn) break;
-        if (e >= opt.max_epochs) return fail(LR_ENOCONV, "inner solver did not converge");
+        if (e >= budget) return fail(LR_ENOCONV, "inner solver did not converge");
       } else if (e >= fixed_epochs) {
         break;
       }
@@ -305,28 +343,45 @@ struct lr_plan_s {
           }
           if (sparse) {
             LR_HIP(lr::csc_step_dot(Xs, b, it, scale + (t - t0) * b, Dlrm, C, PC, st, pd));
-            LR_HIP(lr::rm_decay(d * PC, Grm, Dlrm, lam, eta, st));
+            LR_HIP(lr::rm_decay(d * PC, Grm, Dlrm, lam_in, eta, st));
             LR_HIP(lr::csc_step_scatter(Xs, b, it, C, PC, p, sp_head_slot, sp_head_row, sp_H,
                                         eta, Dlrm, st, pu));
           } else if (bf16_steps) {
             LR_HIP(lr::step_dot_bf16(X, p, b, it, scale + (t - t0) * b, Dh, Dlo, ldD, Ch, Cl,
                                      ldC, PC, st, pd));
-            LR_HIP(lr::step_update_bf16(X, p, b, it, Ch, Cl, ldC, PC, G, Dl, Dh, Dlo, ldD, lam,
+            LR_HIP(lr::step_update_bf16(X, p, b, it, Ch, Cl, ldC, PC, G, Dl, Dh, Dlo, ldD, lam_in,
                                         eta, st, pu));
           } else {
             LR_HIP(lr::step_dot(X, pc, b, it, scale + (t - t0) * b, Dl, C, PCn, st, pd));
-            LR_HIP(lr::step_update(X, pc, b, it, C, PCn, G, Dl, lam, eta, st, pu, df));
+            LR_HIP(lr::step_update(X, pc, b, it, C, PCn, G, Dl, lam_in, eta, st, pu, df));
           }
         }
       }
       if (sparse) LR_HIP(lr::rm_to_cm(Dlrm, d, p, PC, Dl, st));
       if (opt.timing) LR_HIP(hipEventRecord(ev[1], st));
       rep.steps += m;
-      LR_HIP(lr::lincomb(cnt, 1.0, Wt, 1.0, Dl, 0.0, nullptr, Wt, st));
-      if (opt.timing) LR_HIP(hipEventRecord(ev[2], st));
-      LR_CHECK(applyA(Wt, G, pc, -1.0, Wt, lam, Srhs, -1.0));
-      if (opt.timing) LR_HIP(hipEventRecord(ev[3], st));
-      LR_HIP(lr::sumsq(G, cnt, part, dnorm, st));
+      if (accel) {
+        // W_k = W_{k-1} + Delta; G = (lam + kappa) W_k - A W_k - (S + kappa Y_{k-1})
+        LR_HIP(lr::lincomb(cnt, 1.0, Wt, 1.0, Dl, 0.0, nullptr, Wn, st));
+        LR_HIP(lr::lincomb(cnt, 1.0, Srhs, kappa, Yk, 0.0, nullptr, Racc, st));
+        if (opt.timing) LR_HIP(hipEventRecord(ev[2], st));
+        LR_CHECK(applyA(Wn, G, pc, -1.0, Wn, lam_in, Racc, -1.0));
+        if (opt.timing) LR_HIP(hipEventRecord(ev[3], st));
+        // residual of the original system: kappa (W_k - Y_{k-1}) - G
+        LR_HIP(lr::lincomb(cnt, kappa, Wn, -kappa, Yk, -1.0, G, Tm1, st));
+        LR_HIP(lr::sumsq(Tm1, cnt, part, dnorm, st));
+        // Y_k = W_k + beta (W_k - W_{k-1}); the next gradient G - kappa (Y_k - Y_{k-1})
+        LR_HIP(lr::lincomb(cnt, 1.0 + beta, Wn, -beta, Wt, 0.0, nullptr, Ynew, st));
+        LR_HIP(lr::lincomb(cnt, 1.0, G, -kappa, Ynew, kappa, Yk, G, st));
+        std::swap(Yk, Ynew);
+        std::swap(Wt, Wn);
+      } else {
+        LR_HIP(lr::lincomb(cnt, 1.0, Wt, 1.0, Dl, 0.0, nullptr, Wt, st));
+        if (opt.timing) LR_HIP(hipEventRecord(ev[2], st));
+        LR_CHECK(applyA(Wt, G, pc, -1.0, Wt, lam, Srhs, -1.0));
+        if (opt.timing) LR_HIP(hipEventRecord(ev[3], st));
+        LR_HIP(lr::sumsq(G, cnt, part, dnorm, st));
+      }
       LR_CHECK(read(&r, dnorm, sizeof(double)));
       r = std::sqrt(r);
       if (opt.timing) {
@@ -370,7 +425,7 @@ struct lr_plan_s {
   lr_status power_deflated(int cols, int interval, double eps_stop, int* iters, bool* ok);
   lr_status si_deflated(double lam, double eta, int64_t m, int64_t b, double tau,
                         double eps_stop, int32_t first_solve, int target, int cols, int* outer,
-                        bool* ok);
+                        bool* ok, double kappa = 0.0, double beta = 0.0);
   lr_status append_basis(const double* B, int cols);
   lr_status final_rr(const double* Sb, int cols, double* U_out, double* theta_out);
   lr_status solve(double* U_out, double* theta_out, lr_report* out_rep);
@@ -418,11 +473,9 @@ lr_status lr_plan_s::tune_shift(const double* theta, const double* resn, double 
     mu = delta / 10.0;
   }
   for (int r = 0; r < opt.max_shift_rounds; ++r) {
-    int64_t b, m;
-    double eta;
-    constants(t1, lam, mu, &b, &eta, &m);
-    LR_CHECK(svrg_solve(Sest, lam, eta, m, b, solve0 + r, opt.tau_shift, -1, nullptr, nullptr,
-                        pc));
+    const Inner ic = inner_constants(t1, lam, mu);
+    LR_CHECK(svrg_solve(Sest, lam, ic.eta, ic.m, ic.b, solve0 + r, opt.tau_shift, -1, nullptr,
+                        nullptr, pc, ic.kappa, ic.beta));
     LR_CHECK(gram_dd(Sest, pc, Wt, pc, H));
     LR_HIP(lr::eigh(H, pc, vals, Q, st));
     double nu[LR_MAX_P];
@@ -482,7 +535,14 @@ lr_status lr_plan_s::solve(double* U_out, double* theta_out, lr_report* out_rep)
     sched.lambda = lam;
     sched.mu_hat = mu;
     sched.delta_hat = delta;
-    constants(t1, lam, mu, &sched.b, &sched.eta, &sched.m);
+    const Inner ic = inner_constants(t1, lam, mu);
+    sched.b = ic.b;
+    sched.eta = ic.eta;
+    sched.m = ic.m;
+    acc_kappa = ic.kappa;
+    acc_beta = ic.beta;
+    rep.accel_kappa = ic.kappa;
+    rep.accel_beta = ic.beta;
     sched.tau = tau;
     sched.eps_stop = eps_stop;
     sched.first_solve = rounds;
@@ -501,7 +561,8 @@ lr_status lr_plan_s::solve(double* U_out, double* theta_out, lr_report* out_rep)
   for (int ell = 0; ell < L; ++ell) {
     int32_t e = 0;
     LR_CHECK(svrg_solve(S, sched.lambda, sched.eta, sched.m, sched.b, sched.first_solve + ell,
-                        sched.tau, replay ? repochs[ell] : -1, &e, nullptr));
+                        sched.tau, replay ? repochs[ell] : -1, &e, nullptr, -1, acc_kappa,
+                        acc_beta));
     epochs.push_back(e);
     LR_CHECK(gram_dd(S, p, Wt, p, H));
     LR_HIP(lr::eigh(H, p, vals, Q, st));
@@ -589,7 +650,7 @@ lr_status lr_plan_s::power_deflated(int cols, int interval, double eps_stop, int
 // eps_stop.  The block is left in S.
 lr_status lr_plan_s::si_deflated(double lam, double eta, int64_t m, int64_t b, double tau,
                                  double eps_stop, int32_t first_solve, int target, int cols,
-                                 int* outer, bool* ok) {
+                                 int* outer, bool* ok, double kappa, double beta) {
   LR_HIP(lr::gaussian(S, d, cols, opt.seed, stream_word(TAG_SI_INIT, (uint32_t)first_solve), st));
   if (ns > 0) LR_CHECK(deflate(S, S, cols));
   LR_CHECK(cholqr2(S, S, cols));
@@ -597,7 +658,8 @@ lr_status lr_plan_s::si_deflated(double lam, double eta, int64_t m, int64_t b, d
   int ell = 0;
   while (ell < opt.max_outer) {
     int32_t e = 0;
-    LR_CHECK(svrg_solve(S, lam, eta, m, b, first_solve + ell, tau, -1, &e, nullptr, cols));
+    LR_CHECK(svrg_solve(S, lam, eta, m, b, first_solve + ell, tau, -1, &e, nullptr, cols, kappa,
+                        beta));
     epochs.push_back(e);
     LR_CHECK(gram_dd(S, cols, Wt, cols, H));
     LR_HIP(lr::eigh(H, cols, vals, Q, st));
@@ -725,15 +787,16 @@ lr_status lr_plan_s::solve_intervals() {
           break;
         }
       cols = q == kk - 1 ? pc : q + 1;
-      int64_t b, m;
-      double eta;
-      constants(theta[0], lam, mu, &b, &eta, &m);
+      const Inner ic = inner_constants(theta[0], lam, mu);
       sched.lambda = lam;
       sched.mu_hat = mu;
-      sched.eta = eta;
-      sched.m = m;
-      sched.b = b;
-      LR_CHECK(si_deflated(lam, eta, m, b, tau, eps_stop, solve_ctr, q + 1, cols, &iters, &ok));
+      sched.eta = ic.eta;
+      sched.m = ic.m;
+      sched.b = ic.b;
+      rep.accel_kappa = ic.kappa;
+      rep.accel_beta = ic.beta;
+      LR_CHECK(si_deflated(lam, ic.eta, ic.m, ic.b, tau, eps_stop, solve_ctr, q + 1, cols, &iters,
+                           &ok, ic.kappa, ic.beta));
       solve_ctr += iters;
       if (q < kk - 1) {   // keep the interval's own directions: top Ritz vectors in span(S)
         LR_CHECK(applyA(S, Y, cols));
@@ -781,6 +844,7 @@ size_t lr_plan_s::carve(char* base) {
   for (double** b : {&Wrm, &Grm, &Dlrm}) take(b, sparse ? d * PC : 0);
   for (uint16_t** b : {&Dh, &Dlo}) take(b, bf16_steps ? ldD * PC : 0);
   for (double** b : {&Ud, &Dw1, &Dw2}) take(b, adaptive ? d * p : 0);
+  for (double** b : {&Wn, &Ya, &Yb, &Racc}) take(b, accel ? d * p : 0);
   take(&Zt, adaptive ? n * PC : 0);
   take(&Kd, adaptive ? 64 * 64 : 0);
   take(&Vp, adaptive ? (int64_t)lr::zbc_chunks(bmax) * 64 * 64 : 0);
@@ -926,6 +990,9 @@ lr_status plan_check(const lr_matrix* Xm, int k, int p, double eps, const lr_opt
       return fail(LR_EINVAL, "BF16 matrix-core steps need dense BF16 X");
     if (opt->adaptive < 0 || opt->adaptive > 1) return fail(LR_EINVAL, "adaptive must be 0 or 1");
     if (opt->norm < 0 || opt->norm > 1) return fail(LR_EINVAL, "norm must be 0 or 1");
+    if (opt->accel < 0 || opt->accel > 1) return fail(LR_EINVAL, "accel must be 0 or 1");
+    if (opt->accel && opt->replay)
+      return fail(LR_EINVAL, "a replay schedule drives the plain inner solver only");
     if (opt->adaptive &&
         (Xm->layout != LR_DENSE_COLMAJOR || opt->precision != LR_PREC_F64 || opt->replay))
       return fail(LR_EINVAL, "adaptive partitioning needs dense X, FP64 precision, no replay");
@@ -954,6 +1021,7 @@ void plan_shape(lr_plan_s* pl, const lr_matrix* Xm, int k, int p, const lr_optio
   pl->pb.nsplit = pl->sparse ? 0 : lr::pass_nsplit(Xm->d, Xm->n);
   pl->bf16_steps = opt && opt->precision == LR_PREC_BF16_STEPS;
   pl->adaptive = opt && opt->adaptive == 1;
+  pl->accel = opt && opt->accel == 1;
   pl->ldD = lr::pad_to(Xm->d, 32);
   pl->ldC = lr::pad_to(pl->bmax, 32);
 }
@@ -1091,6 +1159,7 @@ void lowrank_options_default(lr_options* o) {
   o->precision = LR_PREC_F64;
   o->adaptive = 0;
   o->norm = 0;
+  o->accel = 0;
 }
 
 lr_status lowrank_plan(lr_plan* out, const lr_matrix* Xm, int k, int p, double eps,
@@ -1251,6 +1320,25 @@ lr_status lowrank_op_svrg_solve(lr_plan plan, const double* S, double lambda, do
   std::vector<double> hist;
   int32_t e = 0;
   LR_CHECK(plan->svrg_solve(S, lambda, eta, m, b, solve, 0.0, epochs, &e, &hist));
+  LR_HIP(hipMemcpyAsync(W_out, plan->Wt, plan->d * plan->p * sizeof(double),
+                        hipMemcpyDeviceToDevice, plan->st));
+  LR_HIP(hipStreamSynchronize(plan->st));
+  if (res_out) std::memcpy(res_out, hist.data(), hist.size() * sizeof(double));
+  return LR_OK;
+}
+
+lr_status lowrank_op_acc_svrg_solve(lr_plan plan, const double* S, double lambda, double kappa,
+                                    double beta, double eta, int64_t m, int64_t b, int32_t solve,
+                                    int32_t epochs, double* W_out, double* res_out) {
+  if (!plan || !S || !W_out || m < 1 || b < 1 || b > plan->n || epochs < 0 || solve < 0 ||
+      !(lambda > 0) || !(eta > 0) || !(kappa >= 0) || !(beta >= 0 && beta < 1))
+    return fail(LR_EINVAL, "bad argument");
+  if (!plan->accel) return fail(LR_EINVAL, "plan made without accel = 1");
+  if (b > plan->bmax) return fail(LR_EINVAL, "minibatch larger than the plan's workspace");
+  if (!plan->prepared) return fail(LR_EINVAL, "call lowrank_op_prepare first");
+  std::vector<double> hist;
+  int32_t e = 0;
+  LR_CHECK(plan->svrg_solve(S, lambda, eta, m, b, solve, 0.0, epochs, &e, &hist, -1, kappa, beta));
   LR_HIP(hipMemcpyAsync(W_out, plan->Wt, plan->d * plan->p * sizeof(double),
                         hipMemcpyDeviceToDevice, plan->st));
   LR_HIP(hipStreamSynchronize(plan->st));

@@ -45,7 +45,7 @@ class lr_options(ctypes.Structure):
                 ("eta_scale", ctypes.c_double), ("tau_shift", ctypes.c_double),
                 ("replay", ctypes.POINTER(lr_schedule)), ("timing", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("adaptive", ctypes.c_int32),
-                ("norm", ctypes.c_int32)]
+                ("norm", ctypes.c_int32), ("accel", ctypes.c_int32)]
 
 
 class lr_report(ctypes.Structure):
@@ -64,7 +64,8 @@ class lr_report(ctypes.Structure):
                 ("interval_s", ctypes.c_int32 * LR_MAX_P), ("interval_q", ctypes.c_int32 * LR_MAX_P),
                 ("interval_branch", ctypes.c_int32 * LR_MAX_P),
                 ("interval_cols", ctypes.c_int32 * LR_MAX_P),
-                ("interval_iters", ctypes.c_int32 * LR_MAX_P)]
+                ("interval_iters", ctypes.c_int32 * LR_MAX_P),
+                ("accel_kappa", ctypes.c_double), ("accel_beta", ctypes.c_double)]
 
 
 class lr_ticket_info(ctypes.Structure):
@@ -112,6 +113,11 @@ SIGNATURES = {
     "lowrank_op_svrg_solve": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                              ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
+    "lowrank_op_acc_svrg_solve": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double,
+                                                 ctypes.c_double, ctypes.c_double,
+                                                 ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                                 ctypes.c_int32, _P,
+                                                 ctypes.POINTER(ctypes.c_double)]),
     "lowrank_server_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.c_int]),
     "lowrank_submit": (ctypes.c_int, [_P, ctypes.POINTER(lr_matrix), ctypes.c_int, ctypes.c_int,
                                       ctypes.c_double, ctypes.POINTER(lr_options), _P,
@@ -244,7 +250,7 @@ def _matrix(Xt):
 
 def make_options(seed=0, shift_mode=0, est_iters=4, max_outer=2000, max_epochs=60,
                  max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0, tau_shift=1e-2,
-                 replay=None, timing=0, precision=0, adaptive=0, norm=0):
+                 replay=None, timing=0, precision=0, adaptive=0, norm=0, accel=0):
     """lr_options plus the host objects it points to (kept alive by the caller)."""
     lib = load_library()
     opt = lr_options()
@@ -256,6 +262,7 @@ def make_options(seed=0, shift_mode=0, est_iters=4, max_outer=2000, max_epochs=6
     opt.precision = precision
     opt.adaptive = adaptive
     opt.norm = norm
+    opt.accel = accel
     keep = None
     if replay is not None:
         sc, arr = replay.to_c()
@@ -281,7 +288,8 @@ class Plan:
 
     def __init__(self, Xt, k, p, eps, seed=0, shift_mode=0, est_iters=4, max_outer=2000,
                  max_epochs=60, max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0,
-                 tau_shift=1e-2, replay=None, timing=0, precision=0, adaptive=0, norm=0):
+                 tau_shift=1e-2, replay=None, timing=0, precision=0, adaptive=0, norm=0,
+                 accel=0):
         import torch
         self.lib = load_library()
         self._mat = _matrix(Xt)
@@ -293,7 +301,7 @@ class Plan:
             seed=seed, shift_mode=shift_mode, est_iters=est_iters, max_outer=max_outer,
             max_epochs=max_epochs, max_shift_rounds=max_shift_rounds, polish=polish, batch=batch,
             eta_scale=eta_scale, tau_shift=tau_shift, replay=replay, timing=timing,
-            precision=precision, adaptive=adaptive, norm=norm)
+            precision=precision, adaptive=adaptive, norm=norm, accel=accel)
         self._opt = opt
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -408,6 +416,16 @@ class Plan:
                                               int(b), int(solve), int(epochs), _ptr(W), res))
         return W.T, np.array(res[:])
 
+    def acc_svrg_solve(self, S, lam, kappa, beta, eta, m, b, solve, epochs):
+        import torch
+        Sc = S.T.contiguous()
+        W = torch.empty_like(Sc)
+        res = (ctypes.c_double * (epochs + 1))()
+        _check(self.lib.lowrank_op_acc_svrg_solve(self._h, _ptr(Sc), float(lam), float(kappa),
+                                                  float(beta), float(eta), int(m), int(b),
+                                                  int(solve), int(epochs), _ptr(W), res))
+        return W.T, np.array(res[:])
+
 
 class Server:
     """Request server over the library's continuous-batching loop.
@@ -505,4 +523,5 @@ def report_dict(rep, p):
                        "branch": "power" if rep.interval_branch[i] == 0 else "shift-invert",
                        "cols": rep.interval_cols[i], "iters": rep.interval_iters[i]}
                       for i in range(min(rep.n_intervals, LR_MAX_P))],
+        "accel_kappa": rep.accel_kappa, "accel_beta": rep.accel_beta,
     }

@@ -100,3 +100,34 @@ def test_precision_option_checks(lib):
     opt.precision = lowrank.LR_PREC_BF16_STEPS
     assert lib.lowrank_plan_bytes(ctypes.byref(m), 2, 4, ctypes.byref(opt), ctypes.byref(out1)) == 0
     assert out1.value > out0.value
+
+
+def test_accel_option_checks(lib):
+    """accel takes 0 or 1 and does not combine with a replay schedule; the
+    momentum buffers add to the workspace."""
+    from paper_1607_02925_amd import lowrank
+    h = ctypes.c_void_p()
+    opt = lowrank.lr_options()
+    lib.lowrank_options_default(ctypes.byref(opt))
+    assert opt.accel == 0
+    m = _mat(100, 500)
+    opt.accel = 2
+    assert lib.lowrank_plan(ctypes.byref(h), ctypes.byref(m), 2, 4, 1e-4, ctypes.byref(opt),
+                            None) == lowrank.LR_EINVAL
+    assert b"accel" in lib.lowrank_last_error()
+    opt.accel = 1
+    ep = (ctypes.c_int32 * 1)(1)
+    opt.replay = ctypes.pointer(lowrank.lr_schedule(lam=1.0, mu_hat=0.1, eta=1e-3, m=4, b=64,
+                                                    first_solve=0, outer=1, n_epochs=1,
+                                                    epochs=ep))
+    assert lib.lowrank_plan(ctypes.byref(h), ctypes.byref(m), 2, 4, 1e-4, ctypes.byref(opt),
+                            None) == lowrank.LR_EINVAL
+    assert b"replay" in lib.lowrank_last_error()
+    opt.replay = None
+    out0, out1 = ctypes.c_size_t(), ctypes.c_size_t()
+    opt.accel = 0
+    assert lib.lowrank_plan_bytes(ctypes.byref(m), 2, 4, ctypes.byref(opt), ctypes.byref(out0)) == 0
+    opt.accel = 1
+    assert lib.lowrank_plan_bytes(ctypes.byref(m), 2, 4, ctypes.byref(opt), ctypes.byref(out1)) == 0
+    # four d x p FP64 buffers; an unused buffer still holds one 256-byte slot
+    assert out1.value >= out0.value + 4 * (100 * 4 * 8 - 256)
