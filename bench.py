@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--batch", type=int, default=0, help="steps: minibatch size (0: 4096)")
     ap.add_argument("--adaptive", type=int, default=0,
                     help="solve: 1 = adaptive partitioning of Algorithm main")
+    ap.add_argument("--accel", type=int, default=0,
+                    help="solve: 1 = accelerated inner solver")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="solve: skip the adaptive / accelerated legs")
     ap.add_argument("--requests", type=int, default=512, help="serve: trace length")
     ap.add_argument("--slots", type=int, default=8, help="serve: concurrent worker slots")
     ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: HBM budget (GB)")
@@ -137,13 +141,14 @@ def cpu_baseline(Xt_dev, w, sched, rep):
                       % (sched.m, sched.b, rep["passes"], rep["total_epochs"])}
 
 
-def adaptive_leg(Xt, w, U_qk, args):
-    """The same workload through the adaptive partitioning of Algorithm main
-    (lr_options.adaptive = 1): solves/s, the intervals it chose, and the
-    principal-angle sine between its U_k and the q = k branch's."""
+def variant_leg(Xt, w, U_qk, args, name, **kw):
+    """The same workload through a variant of the method (kw: adaptive = 1 for
+    the adaptive partitioning of Algorithm main, accel = 1 for the accelerated
+    inner solver): solves/s, what it did, and the principal-angle sine between
+    its U_k and the plain q = k branch's."""
     import torch
     from paper_1607_02925_amd import lowrank
-    plan = lowrank.Plan(Xt, w["k"], w["p"], w["eps"], seed=w["solver_seed"], adaptive=1)
+    plan = lowrank.Plan(Xt, w["k"], w["p"], w["eps"], seed=w["solver_seed"], **kw)
     plan.solve()
     torch.cuda.synchronize()
     lat = []
@@ -155,10 +160,17 @@ def adaptive_leg(Xt, w, U_qk, args):
     Uq = U_qk.contiguous()
     Ua = U.contiguous()
     sin = float(torch.linalg.matrix_norm(Ua - Uq @ (Uq.T @ Ua), ord=2))
+    sc = plan.schedule()
     out = {"solves_per_s": len(lat) / sum(lat), "ms_per_solve": sum(lat) / len(lat) * 1e3,
            "status": st, "passes": rep["passes"], "inner_steps": rep["steps"],
-           "intervals": rep["intervals"], "sin_vs_q_eq_k": sin}
-    log("adaptive: %s" % json.dumps(out))
+           "epochs": rep["total_epochs"], "sin_vs_q_eq_k": sin}
+    if kw.get("adaptive"):
+        out["intervals"] = rep["intervals"]
+    else:
+        out.update(outer=rep["outer"], b=sc.b, m=sc.m)
+    if kw.get("accel"):
+        out.update(kappa=rep["accel_kappa"], beta=rep["accel_beta"])
+    log("%s: %s" % (name, json.dumps(out)))
     return out
 
 
@@ -384,7 +396,7 @@ def main():
         return
 
     plan = lowrank.Plan(Xt, k, p, w["eps"], seed=w["solver_seed"], timing=1,
-                        adaptive=args.adaptive)
+                        adaptive=args.adaptive, accel=args.accel)
 
     if args.mode == "pass":
         Wm = torch.randn((p, d), dtype=torch.float64, device=dev).T
@@ -489,8 +501,13 @@ def main():
                      "bytes_per_launch": dbytes, "avg_launch_ms": dms},
         "cpu_baseline": None,
     }
-    if not args.adaptive:
-        out["adaptive"] = adaptive_leg(Xt, w, U, args)
+    if args.adaptive or args.accel:
+        out["config"]["variant"] = {"adaptive": args.adaptive, "accel": args.accel}
+    elif not args.no_variants:
+        out["adaptive"] = variant_leg(Xt, w, U, args, "adaptive", adaptive=1)
+        out["accel"] = variant_leg(Xt, w, U, args, "accel", accel=1)
+        out["adaptive_accel"] = variant_leg(Xt, w, U, args, "adaptive+accel", adaptive=1,
+                                            accel=1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Xt, dict(w, **data), sched, rep)
     if not args.no_serve:
