@@ -294,6 +294,7 @@ struct lr_plan_s {
     if (hist) hist->push_back(r);
     const uint32_t w3 = stream_word(TAG_SAMPLES, (uint32_t)solve);
     const double lam_in = lam + kappa;   // the steps' shift
+    const bool tiled = !sparse && !bf16_steps;   // Dl tile-major (dense FP64 steps)
     double* Yk = Ya;
     double* Ynew = Yb;
     if (accel)   // Y_0 = W_0; the inner gradient at W_0 equals the original one
@@ -319,7 +320,7 @@ struct lr_plan_s {
         LR_HIP(lr::cm_to_rm(G, d, p, Grm, PC, st));
         LR_HIP(hipMemsetAsync(Dlrm, 0, d * PC * sizeof(double), st));
       } else {
-        LR_HIP(hipMemsetAsync(Dl, 0, cnt * sizeof(double), st));
+        LR_HIP(hipMemsetAsync(Dl, 0, (tiled ? lr::pad16(d) * PCn : cnt) * sizeof(double), st));
         if (bf16_steps) {
           LR_HIP(hipMemsetAsync(Dh, 0, ldD * PC * sizeof(uint16_t), st));
           LR_HIP(hipMemsetAsync(Dlo, 0, ldD * PC * sizeof(uint16_t), st));
@@ -362,7 +363,10 @@ struct lr_plan_s {
       rep.steps += m;
       if (accel) {
         // W_k = W_{k-1} + Delta; G = (lam + kappa) W_k - A W_k - (S + kappa Y_{k-1})
-        LR_HIP(lr::lincomb(cnt, 1.0, Wt, 1.0, Dl, 0.0, nullptr, Wn, st));
+        if (tiled)
+          LR_HIP(lr::tile_add(d, pc, PCn, Wt, Dl, Wn, st));
+        else
+          LR_HIP(lr::lincomb(cnt, 1.0, Wt, 1.0, Dl, 0.0, nullptr, Wn, st));
         LR_HIP(lr::lincomb(cnt, 1.0, Srhs, kappa, Yk, 0.0, nullptr, Racc, st));
         if (opt.timing) LR_HIP(hipEventRecord(ev[2], st));
         LR_CHECK(applyA(Wn, G, pc, -1.0, Wn, lam_in, Racc, -1.0));
@@ -376,7 +380,10 @@ struct lr_plan_s {
         std::swap(Yk, Ynew);
         std::swap(Wt, Wn);
       } else {
-        LR_HIP(lr::lincomb(cnt, 1.0, Wt, 1.0, Dl, 0.0, nullptr, Wt, st));
+        if (tiled)
+          LR_HIP(lr::tile_add(d, pc, PCn, Wt, Dl, Wt, st));
+        else
+          LR_HIP(lr::lincomb(cnt, 1.0, Wt, 1.0, Dl, 0.0, nullptr, Wt, st));
         if (opt.timing) LR_HIP(hipEventRecord(ev[2], st));
         LR_CHECK(applyA(Wt, G, pc, -1.0, Wt, lam, Srhs, -1.0));
         if (opt.timing) LR_HIP(hipEventRecord(ev[3], st));
@@ -838,7 +845,8 @@ size_t lr_plan_s::carve(char* base) {
   take(&w, n);
   take(&cdf, n + 1);
   take(&scratch, 3 * nbt + 8);
-  for (double** b : {&S, &W, &Wt, &G, &Y, &Dl, &Tm1, &Tm2, &Sest}) take(b, dp);
+  for (double** b : {&S, &W, &Wt, &G, &Y, &Tm1, &Tm2, &Sest}) take(b, dp);
+  take(&Dl, std::max<int64_t>(dp, lr::pad16(d) * PC));   // tile-major on the dense FP64 path
   take(&V, d * k);
   take(&Vprev, d * k);
   for (double** b : {&Wrm, &Grm, &Dlrm}) take(b, sparse ? d * PC : 0);
@@ -851,7 +859,7 @@ size_t lr_plan_s::carve(char* base) {
   for (uint16_t** b : {&Ch, &Cl}) take(b, bf16_steps ? ldC * PC : 0);
   take(&T, n * PC);
   take(&Ypart, (int64_t)pb.nsplit * dp);
-  take(&C, bmax * PC);
+  take(&C, lr::pad16(bmax) * PC);   // zero rows past b up to a multiple of 16
   take(&scale, MCH * bmax);
   take(&idx, MCH * bmax);
   take(&part, partn);

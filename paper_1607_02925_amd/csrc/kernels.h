@@ -48,7 +48,18 @@ hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBuf
 hipError_t draw_chunk(int64_t n, const uint64_t* cdf, uint64_t seed, uint32_t t0, int64_t steps,
                       uint32_t epoch, uint32_t word3, int64_t b, int32_t* idx, double* scale,
                       hipStream_t st);
-// Inner step, part 1: C = diag(scale) X_B^T Dl   (C: b x PC row-major).
+// The inner-step difference Dl of the dense FP64 path is kept tile-major: for
+// each 16-row block blk and 16-column slice u a contiguous tile of 256 doubles
+// at (blk * PC / 16 + u) * 256, element (row 4 q + s, column 16 u + c) of the
+// block at (s / 2) * 128 + (16 q + c) * 2 + s % 2 -- lane 16 q + c of the FP64
+// matrix-core B operand reads its four values with two 16-byte loads, and a
+// wave reads the tile as two contiguous 1 KB pieces.  pad16(d) x PC doubles;
+// rows >= d and columns >= p stay 0.
+// out = W + Dl for the d x p column-major W (out may be W).
+hipError_t tile_add(int64_t d, int p, int PC, const double* W, const double* Dl, double* out,
+                    hipStream_t st);
+// Inner step, part 1: C = diag(scale) X_B^T Dl   (C: b x PC row-major, Dl
+// tile-major).  C must hold pad16(b) rows: rows b .. pad16(b) - 1 are set to 0.
 hipError_t step_dot(const XView& X, int p, int64_t b, const int32_t* idx, const double* scale,
                     const double* Dl, double* C, int PC, hipStream_t st,
                     const Probe& pr = Probe());
@@ -64,7 +75,8 @@ struct Deflation {
 };
 int zbc_chunks(int64_t b);
 // Inner step, part 2: Dl <- Dl - eta (G + lam Dl - P X_B C), P = I - Ud Ud^T
-// when deflating (else identity).  b <= 8192.
+// when deflating (else identity).  b <= 8192; Dl tile-major, G d x p column-major;
+// C as written by step_dot (pad16(b) rows, zero past b).
 hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, const double* C,
                        int PC, const double* G, double* Dl, double lam, double eta,
                        hipStream_t st, const Probe& pr = Probe(),

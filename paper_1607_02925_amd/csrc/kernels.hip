@@ -349,6 +349,79 @@ __device__ __forceinline__ void load4raw(const TX* __restrict__ col, int64_t r, 
   }
 }
 
+// Four consecutive elements X[r..r+3] of one column, all rows < d (no bounds
+// logic, so a group of these loads issues back to back).  VEC: column base and
+// r aligned for one vector load.
+template <typename TX, bool VEC>
+__device__ __forceinline__ void load4full(const TX* __restrict__ col, int64_t r, Raw4<TX>& o) {
+  if constexpr (VEC) {
+    if constexpr (sizeof(TX) == 8) {
+      const double2 a = *reinterpret_cast<const double2*>(col + r);
+      const double2 b = *reinterpret_cast<const double2*>(col + r + 2);
+      o.v[0] = a.x; o.v[1] = a.y; o.v[2] = b.x; o.v[3] = b.y;
+    } else if constexpr (sizeof(TX) == 4) {
+      const float4 a = *reinterpret_cast<const float4*>(col + r);
+      o.v[0] = a.x; o.v[1] = a.y; o.v[2] = a.z; o.v[3] = a.w;
+    } else {
+      const uint2 a = *reinterpret_cast<const uint2*>(col + r);
+      o.w[0] = a.x; o.w[1] = a.y;
+    }
+  } else if constexpr (sizeof(TX) == 2) {
+    o.w[0] = (uint32_t)col[r] | ((uint32_t)col[r + 1] << 16);
+    o.w[1] = (uint32_t)col[r + 2] | ((uint32_t)col[r + 3] << 16);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) o.v[s] = col[r + s];
+  }
+}
+
+// Lane l's four B-operand values of one tile of the tile-major difference.
+__device__ __forceinline__ void load_tile_b(const double* __restrict__ tile, int l, double* m) {
+  const double2 a = *reinterpret_cast<const double2*>(tile + 2 * l);
+  const double2 b = *reinterpret_cast<const double2*>(tile + 128 + 2 * l);
+  m[0] = a.x; m[1] = a.y; m[2] = b.x; m[3] = b.y;
+}
+
+// The same rows where some may be >= d: addresses clamped to row d - 1, values
+// of rows >= d set to 0 after the load.
+template <typename TX>
+__device__ __forceinline__ void load4tail(const TX* __restrict__ col, int64_t r, int64_t d,
+                                          Raw4<TX>& o) {
+  TX h[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const TX v = col[min(r + s, d - 1)];
+    h[s] = r + s < d ? v : (TX)0;
+  }
+  if constexpr (sizeof(TX) == 2) {
+    o.w[0] = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+    o.w[1] = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) o.v[s] = h[s];
+  }
+}
+
+// Four consecutive FP64 entries m[r..r+3] of a column of M (all rows < d).
+template <bool VEC>
+__device__ __forceinline__ void load4m(const double* __restrict__ col, int64_t r, double* m) {
+  if constexpr (VEC) {
+    const double2 a = *reinterpret_cast<const double2*>(col + r);
+    const double2 b = *reinterpret_cast<const double2*>(col + r + 2);
+    m[0] = a.x; m[1] = a.y; m[2] = b.x; m[3] = b.y;
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) m[s] = col[r + s];
+  }
+}
+
+// Offset of (row r, column j) in the tile-major inner-step difference with NS
+// 16-column slices (layout described with tile_add in kernels.h).
+__device__ __forceinline__ int64_t dl_off(int64_t r, int j, int NS) {
+  const int rho = (int)(r & 15), q = rho >> 2, s = rho & 3;
+  return ((r >> 4) * NS + (j >> 4)) * 256 + (s >> 1) * 128 + (q * 16 + (j & 15)) * 2 + (s & 1);
+}
+
 constexpr int KSTAGE = 8192;   // largest minibatch; its indices are staged in LDS
 
 // Sum the NW waves' accumulators (NACC 16x16 tiles each) into red[0 .. NACC*256):
@@ -398,13 +471,19 @@ __device__ __forceinline__ void waves_to_lds_seq(double* red, const v4d* acc, in
 // A workgroup owns MT tiles of 16 columns of X and NTW 16-column slices of M
 // (each M fetch feeds MT tiles); its NW waves split the rows.  Each wave
 // issues the loads of G 16-row blocks before it starts their matrix-core
-// work, so G memory latencies overlap.
-template <typename TX, int NW, int NTW, int G, bool GATHER, bool VEC, int MT = 1>
+// work, so G memory latencies overlap: every load of the main loop reads an
+// in-bounds address (invalid columns and the group's overhang point at valid
+// data) and validity is applied to the loaded values, so no load waits on a
+// branch.  The partial last block of rows (d % 16 != 0) is done on its own
+// with clamped, masked loads.  VEC: X and M columns aligned for vector loads.
+// TM: M is the tile-major inner-step difference (zero-padded to pad16(d) x PC,
+// two contiguous 1 KB loads per block and slice) instead of column-major.
+template <typename TX, int NW, int NTW, int G, bool GATHER, bool VEC, int MT = 1, bool TM = false>
 __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64_t ld, int64_t d,
                                                  int64_t ncols, const int32_t* __restrict__ idx,
                                                  const double* __restrict__ M, int p,
                                                  const double* __restrict__ scale,
-                                                 double* __restrict__ out, int PC, bool mvec) {
+                                                 double* __restrict__ out, int PC) {
   __shared__ double red[MT * NTW * 256];
   __shared__ double slots[MT == 1 ? NW * NTW * 256 : 1];
   const int t = threadIdx.x, wave = t / 64, l = t % 64;
@@ -417,74 +496,106 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
   for (int mt = 0; mt < MT; ++mt) {
     const int64_t c = (tile * MT + mt) * 16 + li;
     cval[mt] = c < ncols;
-    int64_t colidx = 0;
-    if (cval[mt]) colidx = GATHER ? (int64_t)idx[c] : c;
-    xcol[mt] = X + colidx * ld;
+    const int64_t cc = cval[mt] ? c : 0;
+    xcol[mt] = X + (GATHER ? (int64_t)idx[cc] : cc) * ld;
   }
   const double* mc[NTW];
   bool jval[NTW];
+  double jf[NTW];
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int j = (nt0 + u) * 16 + li;
     jval[u] = j < p;
+    jf[u] = jval[u] ? 1.0 : 0.0;
     mc[u] = M + (int64_t)(jval[u] ? j : 0) * d;
   }
   v4d acc[MT * NTW];
 #pragma unroll
   for (int a = 0; a < MT * NTW; ++a) acc[a] = v4d{0.0, 0.0, 0.0, 0.0};
-  const int64_t nblk = (d + 15) / 16;
+  const int64_t nblk = (d + 15) / 16, nfull = d / 16;
   const int64_t bpw = (nblk + NW - 1) / NW;
   const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
-  for (int64_t g0 = b0; g0 < b1; g0 += G) {
+  const int64_t bend = min(b1, nfull);
+  for (int64_t g0 = b0; g0 < bend; g0 += G) {
     Raw4<TX> x[G][MT];
     double m[G][NTW][4];
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      const int64_t r = (g0 + i) * 16 + 4 * q;
-      const bool bval = g0 + i < b1;
+      const int64_t blk = g0 + i < bend ? g0 + i : bend - 1;
+      const int64_t r = blk * 16 + 4 * q;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        if (bval && cval[mt])
-          load4raw<TX, VEC>(xcol[mt], r, d, x[i][mt]);
-        else
-          x[i][mt].zero();
-      }
+      for (int mt = 0; mt < MT; ++mt) load4full<TX, VEC>(xcol[mt], r, x[i][mt]);
 #pragma unroll
       for (int u = 0; u < NTW; ++u) {
-        if (bval && jval[u]) {
-          if (mvec && r + 3 < d) {
-            const double2 a = *reinterpret_cast<const double2*>(mc[u] + r);
-            const double2 b = *reinterpret_cast<const double2*>(mc[u] + r + 2);
-            m[i][u][0] = a.x; m[i][u][1] = a.y; m[i][u][2] = b.x; m[i][u][3] = b.y;
-          } else {
+        if constexpr (TM)
+          load_tile_b(M + (blk * (PC / 16) + nt0 + u) * 256, l, m[i][u]);
+        else
+          load4m<VEC>(mc[u], r, m[i][u]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);   // keep the group's loads ahead of its matrix-core work
+    // the group's overhang and the columns >= p of M contribute through a 0/1
+    // factor on the M operand (a multiply, which keeps every load ahead of the
+    // matrix-core work; all operands are finite).  Output rows of invalid X
+    // columns are not stored, so those need no mask.
 #pragma unroll
-            for (int s = 0; s < 4; ++s) m[i][u][s] = (r + s < d) ? mc[u][r + s] : 0.0;
-          }
-        } else {
-          m[i][u][0] = m[i][u][1] = m[i][u][2] = m[i][u][3] = 0.0;
+    for (int i = 0; i < G; ++i) {
+      const double okf = g0 + i < bend ? 1.0 : 0.0;
+#pragma unroll
+      for (int u = 0; u < NTW; ++u) {
+        const double f = TM ? okf : okf * jf[u];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double mb = m[i][u][s] * f;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            acc[mt * NTW + u] = mfma_f64(x[i][mt].get(s), mb, acc[mt * NTW + u]);
+        }
+      }
+    }
+  }
+  if (nfull < nblk && b0 <= nfull && nfull < b1) {   // this wave owns the partial last block
+    const int64_t r = nfull * 16 + 4 * q;
+    Raw4<TX> x[MT];
+    double m[NTW][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) load4tail<TX>(xcol[mt], r, d, x[mt]);
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) {
+      if constexpr (TM) {   // the padded tile holds zeros past row d
+        load_tile_b(M + (nfull * (PC / 16) + nt0 + u) * 256, l, m[u]);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double v = mc[u][min(r + s, d - 1)];
+          m[u][s] = r + s < d ? v : 0.0;
         }
       }
     }
 #pragma unroll
-    for (int i = 0; i < G; ++i)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+      for (int u = 0; u < NTW; ++u)
 #pragma unroll
-        for (int u = 0; u < NTW; ++u)
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-            acc[mt * NTW + u] = mfma_f64(x[i][mt].get(s), m[i][u][s], acc[mt * NTW + u]);
+        for (int s = 0; s < 4; ++s) {
+          const double xa = cval[mt] ? x[mt].get(s) : 0.0;
+          const double mb = jval[u] ? m[u][s] : 0.0;
+          acc[mt * NTW + u] = mfma_f64(xa, mb, acc[mt * NTW + u]);
+        }
   }
   if constexpr (MT == 1)
     waves_to_lds<NW, NTW>(red, slots, acc, q, li);
   else
     waves_to_lds_seq<NW, MT * NTW>(red, acc, q, li);
+  // gathered: rows from ncols up to the next multiple of 16 are written as
+  // zeros (the inner-step update reads whole 16-sample blocks)
+  const int64_t nrows = GATHER ? (ncols + 15) / 16 * 16 : ncols;
   for (int e = t; e < MT * NTW * 256; e += NW * 64) {
     const int a = e / 256, mt = a / NTW, u = a % NTW, i = (e / 16) % 16, jj = e % 16;
     const int64_t cc = (tile * MT + mt) * 16 + i;
-    if (cc < ncols && (nt0 + u) * 16 < PC) {
-      const double sc = scale ? scale[cc] : 1.0;
-      out[cc * PC + (nt0 + u) * 16 + jj] = sc * red[e];
+    if (cc < nrows && (nt0 + u) * 16 < PC) {
+      const double sc = cc < ncols ? (scale ? scale[cc] : 1.0) : 0.0;
+      out[cc * PC + (nt0 + u) * 16 + jj] = cc < ncols ? sc * red[e] : 0.0;
     }
   }
 }
@@ -601,41 +712,72 @@ __global__ __launch_bounds__(NW * 64) void k_step_update(const TX* __restrict__ 
     const int64_t er = r0 + (e % 256) / 16;
     const int ej = (nt0 + e / 256) * 16 + e % 16;
     eval[u] = e < NTW * 256 && er < d && ej < p;
-    eo[u] = eval[u] ? (int64_t)ej * d + er : 0;
+    eo[u] = eval[u] ? dl_off(er, ej, PC / 16) : 0;
     e_dl[u] = eval[u] ? Dl[eo[u]] : 0.0;
-    e_g[u] = eval[u] ? Gr[eo[u]] : 0.0;
+    e_g[u] = eval[u] ? Gr[(int64_t)ej * d + er] : 0.0;
   }
-  for (int64_t e = t; e < b; e += NW * 64) sidx[e] = idx[e];
+  // the index list is padded to whole 16-sample blocks with a valid column
+  const int64_t bpad = (b + 15) / 16 * 16;
+  for (int64_t e = t; e < bpad; e += NW * 64) sidx[e] = idx[e < b ? e : 0];
   __syncthreads();
-  const int64_t row = r0 + lm;
-  const bool rval = row < d;
+  // rows >= d read row d - 1 (their results are not stored)
+  const TX* __restrict__ xrow = X + min(r0 + lm, d - 1);
   v4d acc[NTW];
 #pragma unroll
   for (int u = 0; u < NTW; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t nblk = (b + 15) / 16;
   const int64_t bpw = (nblk + NW - 1) / NW;
   const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
-  for (int64_t g0 = b0; g0 < b1; g0 += G) {
+  // Two register stages of G sample blocks each: the loads of the next stage
+  // are issued before the matrix-core work of the current one, so a wave
+  // always has a stage in flight.  C holds zero rows from b up to the next
+  // multiple of 16 and the index list is padded with a valid column, so
+  // samples past b need no mask; a stage's blocks past the wave's range read
+  // the wave's last block (in bounds) and skip their matrix-core work on a
+  // wave-uniform branch.
+  const int* __restrict__ sq = sidx + 4 * q;
+  const double* __restrict__ cq = C + (int64_t)(4 * q) * PC + nt0 * 16 + lm;
+  struct Stage {
     TX x[G][4];
     double nv[G][4][NTW];
+  };
+  auto load = [&](Stage& S, int64_t g) {
 #pragma unroll
-    for (int i = 0; i < G; ++i)
+    for (int i = 0; i < G; ++i) {
+      const int64_t blk = min(g + i, b1 - 1);
+      const int* __restrict__ si = sq + blk * 16;
+      const double* __restrict__ ci = cq + blk * 16 * PC;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int64_t kc = (g0 + i) * 16 + 4 * q + s;
-        const bool kval = (g0 + i < b1) && kc < b;
-        const int64_t col = kval ? (int64_t)sidx[kc] : 0;
-        x[i][s] = (kval && rval) ? X[col * ld + row] : (TX)0;
+        S.x[i][s] = xrow[(int64_t)si[s] * ld];
 #pragma unroll
-        for (int u = 0; u < NTW; ++u)
-          nv[i][s][u] = (kval && (nt0 + u) * 16 < PC) ? C[kc * PC + (nt0 + u) * 16 + lm] : 0.0;
+        for (int u = 0; u < NTW; ++u) S.nv[i][s][u] = ci[s * PC + u * 16];
       }
+    }
+  };
+  auto compute = [&](const Stage& S, int64_t g) {
 #pragma unroll
-    for (int i = 0; i < G; ++i)
+    for (int i = 0; i < G; ++i) {
+      if (g + i >= b1) break;
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int s = 0; s < 4; ++s) {
+        const double xa = ldx(&S.x[i][s], 0);
 #pragma unroll
-        for (int u = 0; u < NTW; ++u) acc[u] = mfma_f64(ldx(&x[i][s], 0), nv[i][s][u], acc[u]);
+        for (int u = 0; u < NTW; ++u) acc[u] = mfma_f64(xa, S.nv[i][s][u], acc[u]);
+      }
+    }
+  };
+  if (b0 < b1) {
+    Stage A, B;
+    load(A, b0);
+    for (int64_t g = b0; g < b1; g += 2 * G) {
+      load(B, g + G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(A, g);
+      load(A, g + 2 * G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(B, g + G);
+    }
   }
   waves_to_lds<NW, NTW>(red, slots, acc, q, lm);
   if constexpr (DEFL) {
@@ -680,6 +822,18 @@ __global__ __launch_bounds__(NT) void k_zbc(const double* __restrict__ Z, int PC
   double acc = 0.0;
   for (int64_t s = s0; s < s1; ++s) acc = fma(Z[(int64_t)idx[s] * PCZ + t], C[s * PC + j], acc);
   Vp[((int64_t)blockIdx.z * PCZ + t) * PC + j] = acc;
+}
+
+// out[j d + r] = W[j d + r] + Dl(r, j), Dl tile-major.
+__global__ __launch_bounds__(NT) void k_tile_add(int64_t d, int p, int NS,
+                                                 const double* __restrict__ W,
+                                                 const double* __restrict__ Dl,
+                                                 double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= d * p) return;
+  const int64_t r = e % d;
+  const int j = (int)(e / d);
+  out[e] = W[e] + Dl[dl_off(r, j, NS)];
 }
 
 // All draws of `steps` consecutive inner steps (from step t0) of one epoch:
@@ -1210,21 +1364,21 @@ int pass_nsplit(int64_t d, int64_t n) {
   return (int)clampi((2048 + tiles - 1) / tiles, 1, std::max<int64_t>(1, (n + 127) / 128));
 }
 
-template <int NW, int NTW, int G, bool GATHER, int MT = 1>
+template <int NW, int NTW, int G, bool GATHER, int MT = 1, bool TM = false>
 static hipError_t launch_xtm(const XView& X, int64_t ncols, const int32_t* idx, const double* M,
                              int p, const double* scale, double* out, int PC, hipStream_t st,
                              const Probe& pr) {
-  const bool vec = x_vec_ok(X);
-  const bool mvec = X.d % 2 == 0 && (uintptr_t)M % 16 == 0;  // M columns start 16-B aligned
+  // vector loads need aligned X columns and 16-byte aligned M columns
+  const bool vec = x_vec_ok(X) && X.d % 2 == 0 && (uintptr_t)M % 16 == 0;
   const int nt = (p + 15) / 16;
   dim3 grid((unsigned)((ncols + 16 * MT - 1) / (16 * MT)), (unsigned)((nt + NTW - 1) / NTW));
   LR_DISPATCH_DT(X.dt, TX, {
     if (vec)
-      launch(k_xtm<TX, NW, NTW, G, GATHER, true, MT>, grid, dim3(NW * 64), st, pr,
-             (const TX*)X.v, X.ld, X.d, ncols, idx, M, p, scale, out, PC, mvec);
+      launch(k_xtm<TX, NW, NTW, G, GATHER, true, MT, TM>, grid, dim3(NW * 64), st, pr,
+             (const TX*)X.v, X.ld, X.d, ncols, idx, M, p, scale, out, PC);
     else
-      launch(k_xtm<TX, NW, NTW, G, GATHER, false, MT>, grid, dim3(NW * 64), st, pr,
-             (const TX*)X.v, X.ld, X.d, ncols, idx, M, p, scale, out, PC, mvec);
+      launch(k_xtm<TX, NW, NTW, G, GATHER, false, MT, TM>, grid, dim3(NW * 64), st, pr,
+             (const TX*)X.v, X.ld, X.d, ncols, idx, M, p, scale, out, PC);
   });
   return hipGetLastError();
 }
@@ -1276,12 +1430,19 @@ hipError_t step_dot(const XView& X, int p, int64_t b, const int32_t* idx, const 
                     const double* Dl, double* C, int PC, hipStream_t st, const Probe& pr) {
   if (p > 64 || pad16(p) > PC) return hipErrorInvalidValue;
   const int64_t nblk = (X.d + 15) / 16;
-  if (nblk <= 16) return launch_xtm<4, 1, 4, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
-  if (nblk <= 32) return launch_xtm<8, 1, 4, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
-  return launch_xtm<16, 1, 4, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
+  if (nblk <= 16) return launch_xtm<4, 1, 4, true, 1, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
+  if (nblk <= 32) return launch_xtm<8, 1, 4, true, 1, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
+  return launch_xtm<16, 1, 4, true, 1, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
 }
 
 int zbc_chunks(int64_t b) { return (int)((b + ZKS - 1) / ZKS); }
+
+hipError_t tile_add(int64_t d, int p, int PC, const double* W, const double* Dl, double* out,
+                    hipStream_t st) {
+  if (p > PC || PC % 16) return hipErrorInvalidValue;
+  k_tile_add<<<nblocks(d * p), NT, 0, st>>>(d, p, PC / 16, W, Dl, out);
+  return hipGetLastError();
+}
 
 hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, const double* C,
                        int PC, const double* G, double* Dl, double lam, double eta,
@@ -1299,21 +1460,23 @@ hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, con
   // row tile, but twice the workgroups, which this latency-bound step needs
   dim3 grid((unsigned)(((X.d + 15) / 16 + 7) / 8 * 8), (unsigned)((p + 15) / 16));
   // waves split the samples: as many as give each about one prefetch group
-#define LR_UPDATE(NWV, KSV)                                                                   \
-  LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV, {                                           \
-    if (defl)                                                                                 \
-      launch(k_step_update<TX, NWV, 4, 16 * NTV, 1, KSV, true>, grid, dim3(NWV * 64), st, pr, \
-             (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta, df);                   \
-    else                                                                                      \
-      launch(k_step_update<TX, NWV, 4, 16 * NTV, 1, KSV>, grid, dim3(NWV * 64), st, pr,       \
-             (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta, df);                   \
+#define LR_UPDATE(NWV, GV, KSV)                                                                \
+  LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV, {                                            \
+    if (defl)                                                                                  \
+      launch(k_step_update<TX, NWV, GV, 16 * NTV, 1, KSV, true>, grid, dim3(NWV * 64), st, pr, \
+             (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta, df);                    \
+    else                                                                                       \
+      launch(k_step_update<TX, NWV, GV, 16 * NTV, 1, KSV>, grid, dim3(NWV * 64), st, pr,       \
+             (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta, df);                    \
   }))
+  // stage depth (blocks per stage) measured at d = 2048: 2 for small minibatches,
+  // 1 for large ones (16 waves each with 2 stages in flight)
   if (b <= 256) {
-    LR_UPDATE(4, 256);
+    LR_UPDATE(4, 2, 256);
   } else if (b <= 512) {
-    LR_UPDATE(8, 512);
+    LR_UPDATE(8, 2, 512);
   } else {
-    LR_UPDATE(16, KSTAGE);
+    LR_UPDATE(16, 1, KSTAGE);
   }
 #undef LR_UPDATE
   return hipGetLastError();
