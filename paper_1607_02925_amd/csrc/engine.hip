@@ -96,6 +96,7 @@ struct lr_plan_s {
   bool owns_ws = true;             // false: the block belongs to a server arena
   bool owns_host = true;           // false: hpin and ev belong to a server slot
   double *w = nullptr, *S = nullptr, *W = nullptr, *Wt = nullptr, *G = nullptr, *Y = nullptr;
+  double *Wtl = nullptr;   // tile-major copy of the pass operand (dense X)
   double *Dl = nullptr, *Tm1 = nullptr, *Tm2 = nullptr, *Sest = nullptr, *V = nullptr;
   double *Vprev = nullptr, *T = nullptr, *Ypart = nullptr, *C = nullptr, *scale = nullptr;
   double *part = nullptr, *scratch = nullptr;
@@ -149,7 +150,7 @@ struct lr_plan_s {
       LR_HIP(lr::cm_to_rm(Win, d, ncols, Wrm, PC, st));
       LR_HIP(lr::csc_xtw(Xs, Wrm, PC, T, st));
     } else {
-      LR_HIP(lr::pass_xtw(X, Win, ncols, T, PC, st));
+      LR_HIP(lr::pass_xtw(X, Win, ncols, T, PC, Wtl, st));
     }
     return LR_OK;
   }
@@ -698,7 +699,7 @@ lr_status lr_plan_s::append_basis(const double* B, int cols) {
     LR_HIP(hipMemcpyAsync(Tm2, B, d * cols * sizeof(double), hipMemcpyDeviceToDevice, st));
   LR_CHECK(cholqr2(Tm2, Ud + (int64_t)ns * d, cols));
   ns += cols;
-  LR_HIP(lr::pass_xtw(X, Ud, ns, Zt, lr::pad16(ns), st));
+  LR_HIP(lr::pass_xtw(X, Ud, ns, Zt, lr::pad16(ns), Wtl, st));
   return LR_OK;
 }
 
@@ -847,6 +848,7 @@ size_t lr_plan_s::carve(char* base) {
   take(&scratch, 3 * nbt + 8);
   for (double** b : {&S, &W, &Wt, &G, &Y, &Tm1, &Tm2, &Sest}) take(b, dp);
   take(&Dl, std::max<int64_t>(dp, lr::pad16(d) * PC));   // tile-major on the dense FP64 path
+  take(&Wtl, sparse ? 0 : lr::pad16(d) * PC);             // tile-major W for the dense pass
   take(&V, d * k);
   take(&Vprev, d * k);
   for (double** b : {&Wrm, &Grm, &Dlrm}) take(b, sparse ? d * PC : 0);

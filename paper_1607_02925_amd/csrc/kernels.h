@@ -37,8 +37,10 @@ struct PassBufs {
 };
 int pad16(int p);
 int pass_nsplit(int64_t d, int64_t n);
-hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, hipStream_t st,
-                    const Probe& pr = Probe());
+// Wtile: scratch of pad16(d) x pad16(p) doubles (W in the tile-major form, see
+// tile_add below).
+hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, double* Wtile,
+                    hipStream_t st, const Probe& pr = Probe());
 hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBufs& pb,
                    double alpha, const double* A, double beta, const double* B, double gamma,
                    double* out, hipStream_t st, const Probe& pr = Probe());

@@ -402,19 +402,6 @@ __device__ __forceinline__ void load4tail(const TX* __restrict__ col, int64_t r,
   }
 }
 
-// Four consecutive FP64 entries m[r..r+3] of a column of M (all rows < d).
-template <bool VEC>
-__device__ __forceinline__ void load4m(const double* __restrict__ col, int64_t r, double* m) {
-  if constexpr (VEC) {
-    const double2 a = *reinterpret_cast<const double2*>(col + r);
-    const double2 b = *reinterpret_cast<const double2*>(col + r + 2);
-    m[0] = a.x; m[1] = a.y; m[2] = b.x; m[3] = b.y;
-  } else {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) m[s] = col[r + s];
-  }
-}
-
 // Offset of (row r, column j) in the tile-major inner-step difference with NS
 // 16-column slices (layout described with tile_add in kernels.h).
 __device__ __forceinline__ int64_t dl_off(int64_t r, int j, int NS) {
@@ -467,21 +454,24 @@ __device__ __forceinline__ void waves_to_lds_seq(double* red, const v4d* acc, in
 
 // out[c * PC + 16 (NTW y + u) + j] = scale_c * sum_r X[r, col(c)] M[r, 16 (NTW y + u) + j]
 // for c < ncols, j < 16, u < NTW, y = blockIdx.y.  col(c) = idx[c] (GATHER)
-// or c.  M: d x p, column-major, leading dim d; columns >= p count as zero.
-// A workgroup owns MT tiles of 16 columns of X and NTW 16-column slices of M
-// (each M fetch feeds MT tiles); its NW waves split the rows.  Each wave
-// issues the loads of G 16-row blocks before it starts their matrix-core
-// work, so G memory latencies overlap: every load of the main loop reads an
-// in-bounds address (invalid columns and the group's overhang point at valid
-// data) and validity is applied to the loaded values, so no load waits on a
-// branch.  The partial last block of rows (d % 16 != 0) is done on its own
-// with clamped, masked loads.  VEC: X and M columns aligned for vector loads.
-// TM: M is the tile-major inner-step difference (zero-padded to pad16(d) x PC,
-// two contiguous 1 KB loads per block and slice) instead of column-major.
-template <typename TX, int NW, int NTW, int G, bool GATHER, bool VEC, int MT = 1, bool TM = false>
+// or c.  M is tile-major with NSM = ceil(p / 16) slices (the layout of the
+// inner-step difference, zero-padded to pad16(d) x 16 NSM): each 16-row block
+// of a 16-column slice is two contiguous 1 KB loads.  Output slices from NSM
+// up to PC / 16 are written as zeros.  A workgroup owns MT tiles of 16 columns of X and NTW 16-column
+// slices of M (each M fetch feeds MT tiles); its NW waves split the rows.
+// Each wave keeps two register stages of G 16-row blocks: the loads of the
+// next stage are issued before the matrix-core work of the current one.
+// Every load of the main loop reads an in-bounds address (invalid columns
+// read column idx[0] or 0, whose output rows are not stored; a stage's
+// blocks past the wave's range read its last block and skip their
+// matrix-core work on a wave-uniform branch), so no load waits on a branch.
+// The partial last block of rows (d % 16 != 0) is done on its own with
+// clamped, masked X loads (M's padding rows are zero).  VEC: X columns
+// aligned for vector loads.
+template <typename TX, int NW, int NTW, int G, bool GATHER, bool VEC, int MT = 1>
 __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64_t ld, int64_t d,
                                                  int64_t ncols, const int32_t* __restrict__ idx,
-                                                 const double* __restrict__ M, int p,
+                                                 const double* __restrict__ M, int NSM,
                                                  const double* __restrict__ scale,
                                                  double* __restrict__ out, int PC) {
   __shared__ double red[MT * NTW * 256];
@@ -490,6 +480,7 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
   const int li = l % 16, q = l / 16;
   const int64_t tile = blockIdx.x;
   const int nt0 = blockIdx.y * NTW;
+  const int NS = NSM;
   bool cval[MT];
   const TX* xcol[MT];
 #pragma unroll
@@ -499,16 +490,11 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
     const int64_t cc = cval[mt] ? c : 0;
     xcol[mt] = X + (GATHER ? (int64_t)idx[cc] : cc) * ld;
   }
-  const double* mc[NTW];
-  bool jval[NTW];
-  double jf[NTW];
+  // this workgroup's slices; a slice past the last (NTW not dividing the slice
+  // count) reads the last one and its output is not stored
+  int sl[NTW];
 #pragma unroll
-  for (int u = 0; u < NTW; ++u) {
-    const int j = (nt0 + u) * 16 + li;
-    jval[u] = j < p;
-    jf[u] = jval[u] ? 1.0 : 0.0;
-    mc[u] = M + (int64_t)(jval[u] ? j : 0) * d;
-  }
+  for (int u = 0; u < NTW; ++u) sl[u] = min(nt0 + u, NS - 1);
   v4d acc[MT * NTW];
 #pragma unroll
   for (int a = 0; a < MT * NTW; ++a) acc[a] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -516,42 +502,44 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
   const int64_t bpw = (nblk + NW - 1) / NW;
   const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
   const int64_t bend = min(b1, nfull);
-  for (int64_t g0 = b0; g0 < bend; g0 += G) {
+  struct Stage {
     Raw4<TX> x[G][MT];
     double m[G][NTW][4];
+  };
+  auto load = [&](Stage& S, int64_t g) {
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      const int64_t blk = g0 + i < bend ? g0 + i : bend - 1;
+      const int64_t blk = min(g + i, bend - 1);
       const int64_t r = blk * 16 + 4 * q;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) load4full<TX, VEC>(xcol[mt], r, x[i][mt]);
+      for (int mt = 0; mt < MT; ++mt) load4full<TX, VEC>(xcol[mt], r, S.x[i][mt]);
 #pragma unroll
-      for (int u = 0; u < NTW; ++u) {
-        if constexpr (TM)
-          load_tile_b(M + (blk * (PC / 16) + nt0 + u) * 256, l, m[i][u]);
-        else
-          load4m<VEC>(mc[u], r, m[i][u]);
-      }
+      for (int u = 0; u < NTW; ++u) load_tile_b(M + (blk * NS + sl[u]) * 256, l, S.m[i][u]);
     }
-    __builtin_amdgcn_sched_barrier(0);   // keep the group's loads ahead of its matrix-core work
-    // the group's overhang and the columns >= p of M contribute through a 0/1
-    // factor on the M operand (a multiply, which keeps every load ahead of the
-    // matrix-core work; all operands are finite).  Output rows of invalid X
-    // columns are not stored, so those need no mask.
+  };
+  auto compute = [&](const Stage& S, int64_t g) {
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      const double okf = g0 + i < bend ? 1.0 : 0.0;
+      if (g + i >= bend) break;
 #pragma unroll
-      for (int u = 0; u < NTW; ++u) {
-        const double f = TM ? okf : okf * jf[u];
+      for (int u = 0; u < NTW; ++u)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const double mb = m[i][u][s] * f;
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt)
-            acc[mt * NTW + u] = mfma_f64(x[i][mt].get(s), mb, acc[mt * NTW + u]);
-        }
-      }
+            acc[mt * NTW + u] = mfma_f64(S.x[i][mt].get(s), S.m[i][u][s], acc[mt * NTW + u]);
+    }
+  };
+  if (b0 < bend) {
+    Stage A, B;
+    load(A, b0);
+    for (int64_t g = b0; g < bend; g += 2 * G) {
+      load(B, g + G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(A, g);
+      load(A, g + 2 * G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(B, g + G);
     }
   }
   if (nfull < nblk && b0 <= nfull && nfull < b1) {   // this wave owns the partial last block
@@ -561,27 +549,14 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) load4tail<TX>(xcol[mt], r, d, x[mt]);
 #pragma unroll
-    for (int u = 0; u < NTW; ++u) {
-      if constexpr (TM) {   // the padded tile holds zeros past row d
-        load_tile_b(M + (nfull * (PC / 16) + nt0 + u) * 256, l, m[u]);
-      } else {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const double v = mc[u][min(r + s, d - 1)];
-          m[u][s] = r + s < d ? v : 0.0;
-        }
-      }
-    }
+    for (int u = 0; u < NTW; ++u) load_tile_b(M + (nfull * NS + sl[u]) * 256, l, m[u]);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int u = 0; u < NTW; ++u)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const double xa = cval[mt] ? x[mt].get(s) : 0.0;
-          const double mb = jval[u] ? m[u][s] : 0.0;
-          acc[mt * NTW + u] = mfma_f64(xa, mb, acc[mt * NTW + u]);
-        }
+        for (int s = 0; s < 4; ++s)
+          acc[mt * NTW + u] = mfma_f64(x[mt].get(s), m[u][s], acc[mt * NTW + u]);
   }
   if constexpr (MT == 1)
     waves_to_lds<NW, NTW>(red, slots, acc, q, li);
@@ -595,7 +570,7 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
     const int64_t cc = (tile * MT + mt) * 16 + i;
     if (cc < nrows && (nt0 + u) * 16 < PC) {
       const double sc = cc < ncols ? (scale ? scale[cc] : 1.0) : 0.0;
-      out[cc * PC + (nt0 + u) * 16 + jj] = cc < ncols ? sc * red[e] : 0.0;
+      out[cc * PC + (nt0 + u) * 16 + jj] = cc < ncols && nt0 + u < NSM ? sc * red[e] : 0.0;
     }
   }
 }
@@ -822,6 +797,20 @@ __global__ __launch_bounds__(NT) void k_zbc(const double* __restrict__ Z, int PC
   double acc = 0.0;
   for (int64_t s = s0; s < s1; ++s) acc = fma(Z[(int64_t)idx[s] * PCZ + t], C[s * PC + j], acc);
   Vp[((int64_t)blockIdx.z * PCZ + t) * PC + j] = acc;
+}
+
+// The tile-major form (NS slices) of the d x p column-major W, zero-padded to
+// pad16(d) x 16 NS; one thread per output element, in output order.
+__global__ __launch_bounds__(NT) void k_cm_to_tile(const double* __restrict__ W, int64_t d,
+                                                   int p, int NS, double* __restrict__ out,
+                                                   int64_t cnt) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= cnt) return;
+  const int64_t te = e / 256;
+  const int w = (int)(e % 256), l = (w % 128) / 2, s = (w / 128) * 2 + w % 2;
+  const int64_t r = (te / NS) * 16 + 4 * (l / 16) + s;
+  const int j = (int)(te % NS) * 16 + l % 16;
+  out[e] = r < d && j < p ? W[(int64_t)j * d + r] : 0.0;
 }
 
 // out[j d + r] = W[j d + r] + Dl(r, j), Dl tile-major.
@@ -1364,35 +1353,39 @@ int pass_nsplit(int64_t d, int64_t n) {
   return (int)clampi((2048 + tiles - 1) / tiles, 1, std::max<int64_t>(1, (n + 127) / 128));
 }
 
-template <int NW, int NTW, int G, bool GATHER, int MT = 1, bool TM = false>
+template <int NW, int NTW, int G, bool GATHER, int MT = 1>
 static hipError_t launch_xtm(const XView& X, int64_t ncols, const int32_t* idx, const double* M,
                              int p, const double* scale, double* out, int PC, hipStream_t st,
                              const Probe& pr) {
-  // vector loads need aligned X columns and 16-byte aligned M columns
-  const bool vec = x_vec_ok(X) && X.d % 2 == 0 && (uintptr_t)M % 16 == 0;
-  const int nt = (p + 15) / 16;
+  if ((uintptr_t)M % 16) return hipErrorInvalidValue;   // tile loads are 16-byte vectors
+  const bool vec = x_vec_ok(X);
+  const int nt = (p + 15) / 16;   // slices of M's tile layout
   dim3 grid((unsigned)((ncols + 16 * MT - 1) / (16 * MT)), (unsigned)((nt + NTW - 1) / NTW));
   LR_DISPATCH_DT(X.dt, TX, {
     if (vec)
-      launch(k_xtm<TX, NW, NTW, G, GATHER, true, MT, TM>, grid, dim3(NW * 64), st, pr,
-             (const TX*)X.v, X.ld, X.d, ncols, idx, M, p, scale, out, PC);
+      launch(k_xtm<TX, NW, NTW, G, GATHER, true, MT>, grid, dim3(NW * 64), st, pr,
+             (const TX*)X.v, X.ld, X.d, ncols, idx, M, nt, scale, out, PC);
     else
-      launch(k_xtm<TX, NW, NTW, G, GATHER, false, MT, TM>, grid, dim3(NW * 64), st, pr,
-             (const TX*)X.v, X.ld, X.d, ncols, idx, M, p, scale, out, PC);
+      launch(k_xtm<TX, NW, NTW, G, GATHER, false, MT>, grid, dim3(NW * 64), st, pr,
+             (const TX*)X.v, X.ld, X.d, ncols, idx, M, nt, scale, out, PC);
   });
   return hipGetLastError();
 }
 
 // The pass reads every column once; MT column tiles per workgroup share each
 // fetch of W.
-hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, hipStream_t st,
-                    const Probe& pr) {
-  if (p > 64 || pad16(p) > PC) return hipErrorInvalidValue;
+hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, double* Wtile,
+                    hipStream_t st, const Probe& pr) {
+  if (p > 64 || pad16(p) > PC || !Wtile) return hipErrorInvalidValue;
+  // W to the tile-major form (zero-padded), PC = pad16(p) slices of 16 columns
+  const int PCw = pad16(p);
+  const int64_t cnt = (X.d + 15) / 16 * 16 * PCw;
+  k_cm_to_tile<<<nblocks(cnt), NT, 0, st>>>(W, X.d, p, PCw / 16, Wtile, cnt);
   if (p > 32)
-    return launch_xtm<8, 4, 2, false, 2>(X, X.n, nullptr, W, p, nullptr, T, PC, st, pr);
+    return launch_xtm<8, 4, 1, false, 2>(X, X.n, nullptr, Wtile, p, nullptr, T, PC, st, pr);
   if (p > 16)
-    return launch_xtm<8, 2, 2, false, 4>(X, X.n, nullptr, W, p, nullptr, T, PC, st, pr);
-  return launch_xtm<8, 1, 4, false, 4>(X, X.n, nullptr, W, p, nullptr, T, PC, st, pr);
+    return launch_xtm<8, 2, 1, false, 4>(X, X.n, nullptr, Wtile, p, nullptr, T, PC, st, pr);
+  return launch_xtm<8, 1, 2, false, 4>(X, X.n, nullptr, Wtile, p, nullptr, T, PC, st, pr);
 }
 
 hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBufs& pb,
@@ -1430,9 +1423,8 @@ hipError_t step_dot(const XView& X, int p, int64_t b, const int32_t* idx, const 
                     const double* Dl, double* C, int PC, hipStream_t st, const Probe& pr) {
   if (p > 64 || pad16(p) > PC) return hipErrorInvalidValue;
   const int64_t nblk = (X.d + 15) / 16;
-  if (nblk <= 16) return launch_xtm<4, 1, 4, true, 1, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
-  if (nblk <= 32) return launch_xtm<8, 1, 4, true, 1, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
-  return launch_xtm<16, 1, 4, true, 1, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
+  if (nblk <= 16) return launch_xtm<4, 1, 2, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
+  return launch_xtm<8, 1, 2, true>(X, b, idx, Dl, p, scale, C, PC, st, pr);
 }
 
 int zbc_chunks(int64_t b) { return (int)((b + ZKS - 1) / ZKS); }
