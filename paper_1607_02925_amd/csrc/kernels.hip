@@ -8,6 +8,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace lr {
 namespace {
@@ -575,57 +576,138 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
   }
 }
 
+// Four rows r..r+3 of one column with the row index clamped to d - 1 (for the
+// last, ragged 64-row tile: rows >= d read row d - 1; their results are not
+// stored).
+template <typename TX>
+__device__ __forceinline__ void load4clamp(const TX* __restrict__ col, int64_t r, int64_t d,
+                                           Raw4<TX>& o) {
+  if constexpr (sizeof(TX) == 2) {
+    o.w[0] = (uint32_t)col[min(r, d - 1)] | ((uint32_t)col[min(r + 1, d - 1)] << 16);
+    o.w[1] = (uint32_t)col[min(r + 2, d - 1)] | ((uint32_t)col[min(r + 3, d - 1)] << 16);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) o.v[s] = col[min(r + s, d - 1)];
+  }
+}
+
 // Pass, second half: part[split][j * d + r] = sum_{c in split} X[r, c] T[c * PC + j].
 // A workgroup owns 64 rows as four 16-row tiles whose rows interleave
 // (tile mt holds rows r0 + 4 i + mt), so each lane fetches four consecutive
 // rows of one column with a single vector load; all 16 NT columns; the 8 waves
-// split the column range and load G column blocks ahead.
+// split the column range.  Splits hold kper columns, a multiple of 16, so only
+// the last block of the last split can be partial; it is done on its own with
+// clamped, masked loads.  The main loop keeps two register stages of G column
+// blocks with every load in bounds (a stage's blocks past the wave's range
+// read its last block and skip their matrix-core work on a wave-uniform
+// branch).  The grid is remapped so that the row tiles of one split run on one
+// XCD (workgroups go to the 8 XCDs in turn) and share its T rows in one L2.
 template <typename TX, int NT, int G, bool VEC>
 __global__ __launch_bounds__(512) void k_xt_part(const TX* __restrict__ X, int64_t ld, int64_t d,
                                                  int64_t n, const double* __restrict__ T, int PC,
-                                                 int p, double* __restrict__ part) {
+                                                 int p, double* __restrict__ part, int64_t kper) {
   constexpr int NW = 8, MTL = 4;
   __shared__ double red[MTL * NT * 256];
   const int t = threadIdx.x, wave = t / 64, l = t % 64;
   const int lm = l % 16, q = l / 16;
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int RT = gridDim.x, NSP = gridDim.y;
+  int rt = blockIdx.x, split = blockIdx.y;
+  if (RT % 8 == 0 && NSP % 8 == 0) {
+    const int64_t w = blockIdx.x + (int64_t)RT * blockIdx.y;
+    const int64_t k = w / 8;
+    split = (int)((k / RT) * 8 + w % 8);
+    rt = (int)(k % RT);
+  }
+  const int64_t r0 = (int64_t)rt * 64;
   const int64_t rbase = r0 + 4 * lm;
-  const int split = blockIdx.y, nsplit = gridDim.y;
-  const int64_t kper = (n + nsplit - 1) / nsplit;
   const int64_t ks = split * kper;
   const int64_t ke = min(n, ks + kper);
   v4d acc[MTL * NT];
 #pragma unroll
   for (int a = 0; a < MTL * NT; ++a) acc[a] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t nblk = ke > ks ? (ke - ks + 15) / 16 : 0;
+  const int64_t nfull = ke > ks ? (ke - ks) / 16 : 0;
   const int64_t bpw = (nblk + NW - 1) / NW;
   const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
-  for (int64_t g0 = b0; g0 < b1; g0 += G) {
+  const int64_t bend = min(b1, nfull);
+  const double* __restrict__ tq = T + (ks + 4 * q) * PC + lm;
+  const TX* __restrict__ xq = X + (ks + 4 * q) * ld;
+  struct Stage {
     Raw4<TX> x[G][4];
     double nv[G][4][NT];
+  };
+  auto compute = [&](const Stage& S, int64_t g) {
 #pragma unroll
-    for (int i = 0; i < G; ++i)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int64_t kc = ks + (g0 + i) * 16 + 4 * q + s;
-        const bool kval = (g0 + i < b1) && kc < ke;
-        if (kval)
-          load4raw<TX, VEC>(X + kc * ld, rbase, d, x[i][s]);
-        else
-          x[i][s].zero();
-        const double* nrow = T + (kval ? kc : 0) * PC;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) nv[i][s][nt] = kval ? nrow[nt * 16 + lm] : 0.0;
-      }
-#pragma unroll
-    for (int i = 0; i < G; ++i)
+    for (int i = 0; i < G; ++i) {
+      if (g + i >= bend) break;
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int mt = 0; mt < MTL; ++mt)
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt)
-            acc[mt * NT + nt] = mfma_f64(x[i][s].get(mt), nv[i][s][nt], acc[mt * NT + nt]);
+            acc[mt * NT + nt] = mfma_f64(S.x[i][s].get(mt), S.nv[i][s][nt], acc[mt * NT + nt]);
+    }
+  };
+  // the ragged last row tile loads row by row with clamped rows; the others
+  // take one vector load per column
+  auto run = [&](auto ragged) {
+    constexpr bool RG = decltype(ragged)::value;
+    auto load = [&](Stage& S, int64_t g) {
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const int64_t blk = min(g + i, bend - 1);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const TX* __restrict__ col = xq + (blk * 16 + s) * ld;
+          if constexpr (RG)
+            load4clamp<TX>(col, rbase, d, S.x[i][s]);
+          else
+            load4full<TX, VEC>(col, rbase, S.x[i][s]);
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) S.nv[i][s][nt] = tq[(blk * 16 + s) * PC + nt * 16];
+        }
+      }
+    };
+    if (b0 < bend) {
+      Stage A, B;
+      load(A, b0);
+      for (int64_t g = b0; g < bend; g += 2 * G) {
+        load(B, g + G);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(A, g);
+        load(A, g + 2 * G);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(B, g + G);
+      }
+    }
+  };
+  if (r0 + 64 > d)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
+  if (nfull < nblk && b0 <= nfull && nfull < b1) {   // the partial last block of columns
+    Raw4<TX> x[4];
+    double nv[4][NT];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t kc = ks + nfull * 16 + 4 * q + s;
+      const bool kv = kc < ke;
+      const int64_t kcc = kv ? kc : ke - 1;
+      load4clamp<TX>(X + kcc * ld, rbase, d, x[s]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const double v = T[kcc * PC + nt * 16 + lm];
+        nv[s][nt] = kv ? v : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int mt = 0; mt < MTL; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt * NT + nt] = mfma_f64(x[s].get(mt), nv[s][nt], acc[mt * NT + nt]);
   }
   waves_to_lds_seq<NW, MTL * NT>(red, acc, q, lm);
   for (int e = t; e < MTL * NT * 256; e += NW * 64) {
@@ -1393,15 +1475,16 @@ hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBuf
                    double* out, hipStream_t st, const Probe& pr) {
   if (p > 64 || pad16(p) > PC) return hipErrorInvalidValue;
   dim3 grid((unsigned)((X.d + 63) / 64), (unsigned)pb.nsplit);
+  // columns per split: a multiple of 16, so only the last block can be partial
+  const int64_t kper = ((X.n + pb.nsplit - 1) / pb.nsplit + 15) / 16 * 16;
   const bool vec = x_vec_ok(X);
   LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV, {
-    constexpr int GV = NTV <= 2 ? 2 : 1;
     if (vec)
-      launch(k_xt_part<TX, NTV, GV, true>, grid, dim3(512), st, pr, (const TX*)X.v, X.ld, X.d,
-             X.n, T, PC, p, pb.Ypart);
+      launch(k_xt_part<TX, NTV, 1, true>, grid, dim3(512), st, pr, (const TX*)X.v, X.ld, X.d,
+             X.n, T, PC, p, pb.Ypart, kper);
     else
-      launch(k_xt_part<TX, NTV, GV, false>, grid, dim3(512), st, pr, (const TX*)X.v, X.ld, X.d,
-             X.n, T, PC, p, pb.Ypart);
+      launch(k_xt_part<TX, NTV, 1, false>, grid, dim3(512), st, pr, (const TX*)X.v, X.ld, X.d,
+             X.n, T, PC, p, pb.Ypart, kper);
   }));
   const int64_t cnt = X.d * p;
   k_reduce_y<<<nblocks(cnt), NT, 0, st>>>(pb.Ypart, pb.nsplit, cnt, alpha, A, beta, B, gamma, out);
