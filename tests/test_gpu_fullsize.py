@@ -1,0 +1,89 @@
+"""The dense workloads at full size, in the launch configuration the benchmark
+times, against the oracle:
+
+* 2048 x 200000 f32 (the benchmark workload): the sampling table bit for bit,
+  one whole pass X (X^T W) at p = 20, and one whole inner-solver epoch with the
+  schedule a solve of this workload uses (m = 124 steps of b = 2048 samples);
+* 4096 x 500000 bf16: the sampling table bit for bit and one whole pass at
+  p = 48.
+
+The oracle works on column chunks of X (FP64 copies of 1-2 GB), so its memory
+stays bounded; the chunk sums of the pass reorder FP64 additions only.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+CHUNK = 50000
+
+
+def host_columns(Xt, storage, c0, c1):
+    """X[:, c0:c1] in FP64 from the device tensor Xt (n x d)."""
+    import torch
+    part = Xt[c0:c1]
+    if storage == "bf16":
+        part = part.view(torch.int16)
+    return oracle.decode(part.cpu().numpy(), storage)
+
+
+def chunked_norms_and_pass(Xt, storage, n, W):
+    """Column squared norms (each column in row order, as the oracle defines
+    them) and X (X^T W), over column chunks."""
+    w = np.empty(n)
+    Y = np.zeros((W.shape[0], W.shape[1]))
+    for c0 in range(0, n, CHUNK):
+        c1 = min(n, c0 + CHUNK)
+        Xc = host_columns(Xt, storage, c0, c1)
+        w[c0:c1] = oracle.column_sq_norms(Xc)
+        Y += oracle.apply_A(Xc, W)
+        del Xc
+    return w, Y
+
+
+@pytest.mark.parametrize("name", ["planted-2048x200000-f32", "planted-4096x500000-bf16"])
+def test_full_size_table_and_pass(torch_cuda, name):
+    import torch
+    from paper_1607_02925_amd import lowrank
+    w = workloads.workload(name, device="cuda")
+    print("%s generated on the GPU" % name, flush=True)
+    plan = lowrank.Plan(w["Xt"], w["k"], w["p"], w["eps"], seed=w["solver_seed"])
+    wg, cdf, fro2 = plan.prepare()
+    W = np.random.default_rng(11).standard_normal((w["d"], w["p"]))
+    Y = plan.apply_A(torch.from_numpy(W).cuda()).cpu().numpy()
+    wo, Yo = chunked_norms_and_pass(w["Xt"], w["storage"], w["n"], W)
+    _, qc = oracle.build_table(wo)
+    assert np.array_equal(wg.cpu().numpy(), wo)
+    assert np.array_equal(cdf.cpu().numpy().astype(np.uint64), qc)
+    assert fro2 == pytest.approx(float(np.sum(wo)), rel=1e-12)
+    rel = np.linalg.norm(Y - Yo) / np.linalg.norm(Yo)
+    print("%s: table bit-exact, pass rel err %.2e" % (name, rel), flush=True)
+    assert rel <= 1e-13
+
+
+def test_full_size_epoch_bench_schedule(torch_cuda):
+    """One inner-solver epoch on 2048 x 200000 f32 with the schedule of this
+    workload's solve (shift 101.647, eta 9.838e-3, m = 124, b = 2048): the
+    iterate and the residuals agree with the oracle's."""
+    import torch
+    from paper_1607_02925_amd import lowrank
+    name = "planted-2048x200000-f32"
+    w = workloads.workload(name, device="cuda")
+    plan = lowrank.Plan(w["Xt"], w["k"], w["p"], w["eps"], seed=w["solver_seed"])
+    wg, _, _ = plan.prepare()
+    X = host_columns(w["Xt"], w["storage"], 0, w["n"])      # 2048 x 200000 FP64
+    _, qc = oracle.build_table(wg.cpu().numpy())
+    S = oracle.cholqr2(np.random.default_rng(5).standard_normal((w["d"], w["p"])))[0]
+    lam, eta, m, b = 101.64710238615051, 0.009837925024862453, 124, 2048
+    Wg, res_g = plan.svrg_solve(torch.from_numpy(S).cuda(), lam, eta, m, b, 3, 1)
+    Wo, _, res_o = oracle.svrg_solve(X, qc, S, lam, eta, m, b, 0.0, w["solver_seed"], 3, 60,
+                                     fixed_epochs=1)
+    Wg = Wg.cpu().numpy()
+    rel = np.linalg.norm(Wg - Wo) / np.linalg.norm(Wo)
+    print("epoch: W rel err %.2e, residuals gpu %s oracle %s" % (rel, res_g, res_o), flush=True)
+    assert rel <= 1e-11
+    np.testing.assert_allclose(res_g, res_o, rtol=1e-8)
+    assert res_o[-1] < res_o[0]
