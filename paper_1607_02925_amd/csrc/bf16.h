@@ -7,9 +7,13 @@
 // the difference block is what the solver keeps; the full-gradient passes stay
 // FP64, so every epoch restarts from an exactly computed residual.
 //
-// Split layouts (BF16 bit patterns): Dh/Dlo column-major d x PC with leading
-// dimension ldD (a multiple of 8); Ch/Cl row j at [j * ldC, j * ldC + b)
-// (ldC a multiple of 32).  Padding rows/columns must hold zeros.
+// Split layouts (BF16 bit patterns), in the matrix-core B-operand order: for
+// each block of 32 k (rows of d for Dh/Dlo, samples for Ch/Cl) and each
+// 16-column slice, a contiguous tile of 512 values in which lane l = 16 q + c
+// holds k = 8 q .. 8 q + 7 of column c.  Element (k, j) sits at
+// ((k / 32) (PC / 16) + j / 16) 512 + (((k % 32) / 8) 16 + j % 16) 8 + k % 8.
+// Dh/Dlo hold ldD x PC values (ldD = pad32(d)), Ch/Cl ldC x PC (ldC >=
+// pad32(b)); rows past d (samples past b) and columns past p must hold zeros.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -34,64 +34,116 @@ __device__ __forceinline__ void split2(double x, uint16_t* hi, uint16_t* lo) {
   *lo = bf16_rne((float)(x - (double)__uint_as_float((uint32_t)h << 16)));
 }
 
-// Eight consecutive BF16 values of one column from row r (zeros beyond d).
+// The split operands (Dh/Dlo of the step difference, Ch/Cl of C) are kept in
+// the matrix-core B-operand order: for each block of 32 k (rows of d, or
+// samples) and each 16-column slice a contiguous tile of 512 BF16 values in
+// which lane l = 16 q + c holds k = 8 q .. 8 q + 7 of column c.  A wave reads
+// a tile as one contiguous 1 KB load; rows past d (or samples past b) and
+// columns past p stay zero.
+__device__ __forceinline__ int64_t bt_off(int64_t k, int j, int NS) {
+  const int w = (int)(k & 31);
+  return (((k >> 5) * NS + (j >> 4)) * 64 + (w >> 3) * 16 + (j & 15)) * 8 + (w & 7);
+}
+
+__device__ __forceinline__ uint4 tile_b(const uint16_t* __restrict__ base, int64_t kb, int u,
+                                        int NS, int l) {
+  return *reinterpret_cast<const uint4*>(base + ((kb * NS + u) * 64 + l) * 8);
+}
+
+// Eight consecutive BF16 values of one column from row r, all rows < d.
 template <bool VEC>
-__device__ __forceinline__ uint4 load8(const uint16_t* __restrict__ col, int64_t r, int64_t d) {
-  if (VEC && r + 7 < d) return *reinterpret_cast<const uint4*>(col + r);
+__device__ __forceinline__ uint4 load8full(const uint16_t* __restrict__ col, int64_t r) {
+  if constexpr (VEC) return *reinterpret_cast<const uint4*>(col + r);
   uint32_t w[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t a = r + 2 * q < d ? (uint32_t)col[r + 2 * q] : 0u;
-    const uint32_t b = r + 2 * q + 1 < d ? (uint32_t)col[r + 2 * q + 1] : 0u;
-    w[q] = a | (b << 16);
+  for (int h = 0; h < 4; ++h) w[h] = (uint32_t)col[r + 2 * h] | ((uint32_t)col[r + 2 * h + 1] << 16);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// The same with rows >= d read as zero (addresses clamped to row d - 1).
+__device__ __forceinline__ uint4 load8tail(const uint16_t* __restrict__ col, int64_t r, int64_t d) {
+  uint32_t w[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int64_t ra = r + 2 * h, rb = ra + 1;
+    const uint32_t va = col[min(ra, d - 1)], vb = col[min(rb, d - 1)];
+    w[h] = (ra < d ? va : 0u) | ((rb < d ? vb : 0u) << 16);
   }
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
 // C = diag(scale) X_B^T (Dh + Dlo) for 16 samples x NTW 16-column slices; the
-// NW waves split the rows in 32-row blocks and fetch G blocks ahead.
+// NW waves split the rows in 32-row blocks.  Two register stages of G blocks:
+// the next stage's loads are issued before the current stage's matrix-core
+// work.  Every load reads an in-bounds address: samples past b read column
+// idx[0] (their rows of C are not stored), a stage's blocks past the wave's
+// range re-read its last block and skip their matrix-core work on a
+// wave-uniform branch, and the partial last block of rows is done on its own
+// with clamped, zeroed X loads (the split tiles hold zeros past d).
 template <int NW, int NTW, int G, bool VEC>
 __global__ __launch_bounds__(NW * 64) void k_sdot_bf16(
     const uint16_t* __restrict__ X, int64_t ld, int64_t d, int64_t b,
     const int32_t* __restrict__ idx, const double* __restrict__ scale,
-    const uint16_t* __restrict__ Dh, const uint16_t* __restrict__ Dlo, int64_t ldD,
-    uint16_t* __restrict__ Ch, uint16_t* __restrict__ Cl, int64_t ldC, int PC) {
+    const uint16_t* __restrict__ Dh, const uint16_t* __restrict__ Dlo,
+    uint16_t* __restrict__ Ch, uint16_t* __restrict__ Cl, int PC) {
   __shared__ double slots[NW * NTW * 256];
   const int t = threadIdx.x, wave = t / 64, l = t % 64, li = l % 16, q = l / 16;
+  const int NS = PC / 16;
   const int64_t s0 = (int64_t)blockIdx.x * 16;
-  const int nt0 = blockIdx.y * NTW;
   const int64_t s = s0 + li;
-  const bool sval = s < b;
-  const uint16_t* xcol = X + (sval ? (int64_t)idx[s] : 0) * ld;
-  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  const uint16_t* __restrict__ xcol = X + (int64_t)idx[s < b ? s : 0] * ld;
   f32x4 ah[NTW], al[NTW];
 #pragma unroll
   for (int u = 0; u < NTW; ++u) ah[u] = al[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int64_t nkb = (d + 31) / 32;
+  const int64_t nkb = (d + 31) / 32, nfull = d / 32;
   const int64_t kpw = (nkb + NW - 1) / NW;
   const int64_t k0 = wave * kpw, k1 = min(nkb, k0 + kpw);
-  for (int64_t g0 = k0; g0 < k1; g0 += G) {
+  const int64_t kend = min(k1, nfull);
+  struct Stage {
     uint4 xa[G], bh[G][NTW], bl[G][NTW];
+  };
+  auto load = [&](Stage& S, int64_t g) {
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      const int64_t r = (g0 + i) * 32 + 8 * q;
-      const bool kv = g0 + i < k1;
-      xa[i] = (kv && sval) ? load8<VEC>(xcol, r, d) : z4;
+      const int64_t kb = min(g + i, kend - 1);
+      S.xa[i] = load8full<VEC>(xcol, kb * 32 + 8 * q);
 #pragma unroll
       for (int u = 0; u < NTW; ++u) {
-        const bool jv = kv && (nt0 + u) * 16 < PC;
-        const int64_t o = (int64_t)((nt0 + u) * 16 + li) * ldD + r;
-        bh[i][u] = jv ? *reinterpret_cast<const uint4*>(Dh + o) : z4;
-        bl[i][u] = jv ? *reinterpret_cast<const uint4*>(Dlo + o) : z4;
+        S.bh[i][u] = tile_b(Dh, kb, u, NS, l);
+        S.bl[i][u] = tile_b(Dlo, kb, u, NS, l);
       }
     }
+  };
+  auto compute = [&](const Stage& S, int64_t g) {
 #pragma unroll
-    for (int i = 0; i < G; ++i)
+    for (int i = 0; i < G; ++i) {
+      if (g + i >= kend) break;
 #pragma unroll
       for (int u = 0; u < NTW; ++u) {
-        ah[u] = mfma_bf16(xa[i], bh[i][u], ah[u]);
-        al[u] = mfma_bf16(xa[i], bl[i][u], al[u]);
+        ah[u] = mfma_bf16(S.xa[i], S.bh[i][u], ah[u]);
+        al[u] = mfma_bf16(S.xa[i], S.bl[i][u], al[u]);
       }
+    }
+  };
+  if (k0 < kend) {
+    Stage A, B;
+    load(A, k0);
+    for (int64_t g = k0; g < kend; g += 2 * G) {
+      load(B, g + G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(A, g);
+      load(A, g + 2 * G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(B, g + G);
+    }
+  }
+  if (nfull < nkb && k0 <= nfull && nfull < k1) {   // the partial last block of rows
+    const uint4 xa = load8tail(xcol, nfull * 32 + 8 * q, d);
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) {
+      ah[u] = mfma_bf16(xa, tile_b(Dh, nfull, u, NS, l), ah[u]);
+      al[u] = mfma_bf16(xa, tile_b(Dlo, nfull, u, NS, l), al[u]);
+    }
   }
   double* mine = slots + wave * (NTW * 256);
 #pragma unroll
@@ -106,8 +158,8 @@ __global__ __launch_bounds__(NW * 64) void k_sdot_bf16(
     for (int w = 1; w < NW; ++w) sum += slots[w * (NTW * 256) + e];
     const int u = e / 256, i = (e / 16) % 16, jj = e % 16;
     const int64_t ss = s0 + i;
-    if (ss < b && (nt0 + u) * 16 < PC) {
-      const int64_t o = (int64_t)((nt0 + u) * 16 + jj) * ldC + ss;
+    if (ss < b) {
+      const int64_t o = bt_off(ss, u * 16 + jj, NS);
       split2(scale[ss] * sum, &Ch[o], &Cl[o]);
     }
   }
@@ -115,20 +167,27 @@ __global__ __launch_bounds__(NW * 64) void k_sdot_bf16(
 
 // U = X_B (Ch + Cl)^T for 16 rows x NTW slices; Dl <- Dl - eta (G + lam Dl - U)
 // for r < d, j < p, and the new Dl is split into Dh/Dlo.  The NW waves split
-// the samples in 32-sample blocks (indices staged in LDS).
+// the samples in 32-sample blocks; the indices are staged in LDS, padded to a
+// multiple of 32 with a valid column (the split C tiles hold zeros past b), so
+// every block is whole.  Two register stages as in k_sdot_bf16; rows past d
+// read row d - 1 (their results are not stored).  The grid (a multiple of 8
+// tiles) is remapped so that each XCD owns a contiguous run of row tiles and
+// the pieces of a gathered column's cache line meet in one L2.
 template <int NW, int NTW, int G>
 __global__ __launch_bounds__(NW * 64) void k_supd_bf16(
     const uint16_t* __restrict__ X, int64_t ld, int64_t d, int64_t b,
     const int32_t* __restrict__ idx, const uint16_t* __restrict__ Ch,
-    const uint16_t* __restrict__ Cl, int64_t ldC, int PC, int p, const double* __restrict__ Gr,
+    const uint16_t* __restrict__ Cl, int PC, int p, const double* __restrict__ Gr,
     double* __restrict__ Dl, uint16_t* __restrict__ Dh, uint16_t* __restrict__ Dlo,
-    int64_t ldD, double lam, double eta) {
+    double lam, double eta) {
   constexpr int EPT = (NTW * 256 + NW * 64 - 1) / (NW * 64);
   __shared__ double slots[NW * NTW * 256];
   __shared__ int sidx[KST];
   const int t = threadIdx.x, wave = t / 64, l = t % 64, li = l % 16, q = l / 16;
-  const int64_t r0 = (int64_t)blockIdx.x * 16;
-  const int nt0 = blockIdx.y * NTW;
+  const int NS = PC / 16;
+  const int64_t tile = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  const int64_t r0 = tile * 16;
+  if (r0 >= d) return;
   // the epilogue's operands are fetched now, so their latency overlaps the loop
   double e_dl[EPT], e_g[EPT];
   int64_t eo[EPT], er[EPT];
@@ -138,53 +197,66 @@ __global__ __launch_bounds__(NW * 64) void k_supd_bf16(
   for (int a = 0; a < EPT; ++a) {
     const int e = t + a * NW * 64;
     er[a] = r0 + (e % 256) / 16;
-    ej[a] = (nt0 + e / 256) * 16 + e % 16;
+    ej[a] = e / 256 * 16 + e % 16;
     ev[a] = e < NTW * 256 && er[a] < d && ej[a] < p;
     eo[a] = ev[a] ? (int64_t)ej[a] * d + er[a] : 0;
     e_dl[a] = ev[a] ? Dl[eo[a]] : 0.0;
     e_g[a] = ev[a] ? Gr[eo[a]] : 0.0;
   }
-  for (int64_t e = t; e < b; e += NW * 64) sidx[e] = idx[e];
+  const int64_t bpad = (b + 31) / 32 * 32;
+  for (int64_t e = t; e < bpad; e += NW * 64) sidx[e] = idx[e < b ? e : 0];
   __syncthreads();
-  const int64_t row = r0 + li;
-  const bool rval = row < d;
-  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  const uint16_t* __restrict__ xrow = X + min(r0 + li, d - 1);
   f32x4 ah[NTW], al[NTW];
 #pragma unroll
   for (int u = 0; u < NTW; ++u) ah[u] = al[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int64_t nkb = (b + 31) / 32;
+  const int64_t nkb = bpad / 32;
   const int64_t kpw = (nkb + NW - 1) / NW;
   const int64_t k0 = wave * kpw, k1 = min(nkb, k0 + kpw);
-  for (int64_t g0 = k0; g0 < k1; g0 += G) {
+  const int* __restrict__ sq = sidx + 8 * q;
+  struct Stage {
     uint4 xa[G], ch[G][NTW], cl[G][NTW];
+  };
+  auto load = [&](Stage& S, int64_t g) {
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      const int64_t sb = (g0 + i) * 32 + 8 * q;
-      const bool kv = g0 + i < k1;
+      const int64_t kb = min(g + i, k1 - 1);
+      const int* __restrict__ si = sq + kb * 32;
       uint32_t w[4];
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const int64_t sa = sb + 2 * h, sc = sa + 1;
-        const uint32_t a = (kv && rval && sa < b) ? (uint32_t)X[(int64_t)sidx[sa] * ld + row] : 0u;
-        const uint32_t c = (kv && rval && sc < b) ? (uint32_t)X[(int64_t)sidx[sc] * ld + row] : 0u;
-        w[h] = a | (c << 16);
-      }
-      xa[i] = make_uint4(w[0], w[1], w[2], w[3]);
+      for (int h = 0; h < 4; ++h)
+        w[h] = (uint32_t)xrow[(int64_t)si[2 * h] * ld] |
+               ((uint32_t)xrow[(int64_t)si[2 * h + 1] * ld] << 16);
+      S.xa[i] = make_uint4(w[0], w[1], w[2], w[3]);
 #pragma unroll
       for (int u = 0; u < NTW; ++u) {
-        const bool jv = kv && (nt0 + u) * 16 < PC;
-        const int64_t o = (int64_t)((nt0 + u) * 16 + li) * ldC + sb;
-        ch[i][u] = jv ? *reinterpret_cast<const uint4*>(Ch + o) : z4;
-        cl[i][u] = jv ? *reinterpret_cast<const uint4*>(Cl + o) : z4;
+        S.ch[i][u] = tile_b(Ch, kb, u, NS, l);
+        S.cl[i][u] = tile_b(Cl, kb, u, NS, l);
       }
     }
+  };
+  auto compute = [&](const Stage& S, int64_t g) {
 #pragma unroll
-    for (int i = 0; i < G; ++i)
+    for (int i = 0; i < G; ++i) {
+      if (g + i >= k1) break;
 #pragma unroll
       for (int u = 0; u < NTW; ++u) {
-        ah[u] = mfma_bf16(xa[i], ch[i][u], ah[u]);
-        al[u] = mfma_bf16(xa[i], cl[i][u], al[u]);
+        ah[u] = mfma_bf16(S.xa[i], S.ch[i][u], ah[u]);
+        al[u] = mfma_bf16(S.xa[i], S.cl[i][u], al[u]);
       }
+    }
+  };
+  if (k0 < k1) {
+    Stage A, B;
+    load(A, k0);
+    for (int64_t g = k0; g < k1; g += 2 * G) {
+      load(B, g + G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(A, g);
+      load(A, g + 2 * G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(B, g + G);
+    }
   }
   double* mine = slots + wave * (NTW * 256);
 #pragma unroll
@@ -202,7 +274,7 @@ __global__ __launch_bounds__(NW * 64) void k_supd_bf16(
     for (int w = 1; w < NW; ++w) U += slots[w * (NTW * 256) + e];
     const double x = e_dl[a] - eta * (e_g[a] + lam * e_dl[a] - U);
     Dl[eo[a]] = x;
-    const int64_t o = (int64_t)ej[a] * ldD + er[a];
+    const int64_t o = bt_off(er[a], ej[a], NS);
     split2(x, &Dh[o], &Dlo[o]);
   }
 }
@@ -247,18 +319,18 @@ hipError_t step_dot_bf16(const XView& X, int p, int64_t b, const int32_t* idx,
                          int64_t ldD, uint16_t* Ch, uint16_t* Cl, int64_t ldC, int PC,
                          hipStream_t st, const Probe& pr) {
   if (X.dt != 2 || PC % 16 || PC > 64 || p > PC || ldD % 32 || ldD < X.d || ldC % 32 ||
-      ldC < pad_to(b, 32))
+      ldC < pad_to(b, 32) || (uintptr_t)Dh % 16 || (uintptr_t)Dlo % 16)
     return hipErrorInvalidValue;
   const bool vec = X.ld % 8 == 0 && (uintptr_t)X.v % 16 == 0;
   const dim3 grid((unsigned)((b + 15) / 16), 1);
   BF_DISPATCH_NTW(PC / 16, NTW, {
-    constexpr int GB = NTW <= 2 ? 4 : 2;
+    constexpr int GB = NTW <= 2 ? 2 : 1;
     if (vec)
       launch_bf(k_sdot_bf16<8, NTW, GB, true>, grid, dim3(512), st, pr, (const uint16_t*)X.v,
-                X.ld, X.d, b, idx, scale, Dh, Dlo, ldD, Ch, Cl, ldC, PC);
+                X.ld, X.d, b, idx, scale, Dh, Dlo, Ch, Cl, PC);
     else
       launch_bf(k_sdot_bf16<8, NTW, GB, false>, grid, dim3(512), st, pr, (const uint16_t*)X.v,
-                X.ld, X.d, b, idx, scale, Dh, Dlo, ldD, Ch, Cl, ldC, PC);
+                X.ld, X.d, b, idx, scale, Dh, Dlo, Ch, Cl, PC);
   });
   return hipGetLastError();
 }
@@ -269,13 +341,13 @@ hipError_t step_update_bf16(const XView& X, int p, int64_t b, const int32_t* idx
                             int64_t ldD, double lam, double eta, hipStream_t st,
                             const Probe& pr) {
   if (X.dt != 2 || b > KST || PC % 16 || PC > 64 || p > PC || ldD % 32 || ldD < X.d ||
-      ldC % 32 || ldC < pad_to(b, 32))
+      ldC % 32 || ldC < pad_to(b, 32) || (uintptr_t)Ch % 16 || (uintptr_t)Cl % 16)
     return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((X.d + 15) / 16), 1);
+  const dim3 grid((unsigned)(((X.d + 15) / 16 + 7) / 8 * 8), 1);
   BF_DISPATCH_NTW(PC / 16, NTW, {
-    constexpr int GB = NTW <= 2 ? 4 : 2;
+    constexpr int GB = NTW <= 2 ? 2 : 1;
     launch_bf(k_supd_bf16<8, NTW, GB>, grid, dim3(512), st, pr, (const uint16_t*)X.v, X.ld, X.d,
-              b, idx, Ch, Cl, ldC, PC, p, G, Dl, Dh, Dlo, ldD, lam, eta);
+              b, idx, Ch, Cl, PC, p, G, Dl, Dh, Dlo, lam, eta);
   });
   return hipGetLastError();
 }
