@@ -77,22 +77,40 @@ __device__ __forceinline__ void draw_one(const uint64_t* __restrict__ cdf, int64
 // ---------------------------------------------------------------------------
 // Column squared norms, summed in row order with separate multiply and add
 // roundings (no fused multiply-add), so every implementation agrees bit for bit.
+// A workgroup owns CN_COLS columns and walks down them CN_ROWS rows at a
+// time: the tile is loaded with consecutive threads on consecutive rows of a
+// column (coalesced), then each of CN_COLS threads adds its column's values
+// from LDS in row order.
+constexpr int CN_COLS = 64, CN_ROWS = 64;
 template <typename TX>
 __global__ __launch_bounds__(NT) void k_colnorm(const TX* __restrict__ X, int64_t ld, int64_t d,
                                                 int64_t n, double* __restrict__ w,
                                                 int* __restrict__ bad) {
 #pragma clang fp contract(off)
-  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (i >= n) return;
-  const TX* col = X + i * ld;
+  __shared__ double tile[CN_COLS][CN_ROWS + 1];
+  const int t = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * CN_COLS;
   double s = 0.0;
-  for (int64_t r = 0; r < d; ++r) {
-    const double x = ldx(col, r);
-    const double sq = x * x;
-    s = s + sq;
+  for (int64_t r0 = 0; r0 < d; r0 += CN_ROWS) {
+    for (int e = t; e < CN_COLS * CN_ROWS; e += NT) {
+      const int c = e / CN_ROWS, r = e % CN_ROWS;
+      tile[c][r] = (c0 + c < n && r0 + r < d) ? ldx(X + (c0 + c) * ld, r0 + r) : 0.0;
+    }
+    __syncthreads();
+    if (t < CN_COLS) {
+      const int rn = (int)min<int64_t>(CN_ROWS, d - r0);
+      for (int r = 0; r < rn; ++r) {
+        const double x = tile[t][r];
+        const double sq = x * x;
+        s = s + sq;
+      }
+    }
+    __syncthreads();
   }
-  w[i] = s;
-  if (!isfinite(s)) atomicOr(bad, 1);
+  if (t < CN_COLS && c0 + t < n) {
+    w[c0 + t] = s;
+    if (!isfinite(s)) atomicOr(bad, 1);
+  }
 }
 
 constexpr int TB = 1024;  // table elements per block (4 per thread)
@@ -1376,8 +1394,8 @@ static void launch(K kernel, dim3 grid, dim3 block, hipStream_t st, const Probe&
 
 hipError_t colnorms(const XView& X, double* w, int* bad, hipStream_t st) {
   LR_DISPATCH_DT(X.dt, TX,
-                 k_colnorm<TX><<<nblocks(X.n), NT, 0, st>>>((const TX*)X.v, X.ld, X.d, X.n, w,
-                                                            bad));
+                 k_colnorm<TX><<<nblocks(X.n, CN_COLS), NT, 0, st>>>((const TX*)X.v, X.ld, X.d,
+                                                                     X.n, w, bad));
   return hipGetLastError();
 }
 
