@@ -287,6 +287,16 @@ __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// v_mfma_f64_4x4x4f64, four 4 x 4 blocks: lane l = 16 k + 4 blk + m supplies
+// A[blk][m][k] and lane 16 k + 4 blk + n supplies B[blk][k][n]; lane
+// 16 m + 4 blk + n receives D[blk][m][n] (checked on the device).  With the
+// 16x16x4 A operand in place (lane l: row l % 16, k = l / 16) the four blocks
+// cover the same 16 rows against four columns of B, at a quarter of the
+// 16x16x4 cost (16 against 64 cycles per SIMD, measured).
+__device__ __forceinline__ double mfma_f64_4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
 // Four consecutive elements X[r..r+3] of one column, widened to FP64.  VEC:
 // the column base and r are aligned for one vector load; rows >= d read 0.
 template <typename TX, bool VEC>
@@ -475,9 +485,10 @@ __device__ __forceinline__ void waves_to_lds_seq(double* red, const v4d* acc, in
 // for c < ncols, j < 16, u < NTW, y = blockIdx.y.  col(c) = idx[c] (GATHER)
 // or c.  M is tile-major with NSM = ceil(p / 16) slices (the layout of the
 // inner-step difference, zero-padded to pad16(d) x 16 NSM): each 16-row block
-// of a 16-column slice is two contiguous 1 KB loads.  Output slices from NSM
-// up to PC / 16 are written as zeros.  A workgroup owns MT tiles of 16 columns of X and NTW 16-column
-// slices of M (each M fetch feeds MT tiles); its NW waves split the rows.
+// of a 16-column slice is two contiguous 1 KB loads.  Output slices that the
+// grid covers past NSM are written as zeros.  A workgroup owns MT tiles of 16
+// columns of X and NTW 16-column slices of M (each M fetch feeds MT tiles);
+// its NW waves split the rows.
 // Each wave keeps two register stages of G 16-row blocks: the loads of the
 // next stage are issued before the matrix-core work of the current one.
 // Every load of the main loop reads an in-bounds address (invalid columns
@@ -486,15 +497,20 @@ __device__ __forceinline__ void waves_to_lds_seq(double* red, const v4d* acc, in
 // matrix-core work on a wave-uniform branch), so no load waits on a branch.
 // The partial last block of rows (d % 16 != 0) is done on its own with
 // clamped, masked X loads (M's padding rows are zero).  VEC: X columns
-// aligned for vector loads.
-template <typename TX, int NW, int NTW, int G, bool GATHER, bool VEC, int MT = 1>
+// aligned for vector loads.  R4 > 0 (with nt0 = 0): after the NTW full
+// slices, 4 R4 more columns of M (from slice NTW) are done with 4x4x4 matrix
+// cores instead of a whole padded 16-column slice; output columns from
+// 16 NTW + 4 R4 up to PC are written as zeros.
+template <typename TX, int NW, int NTW, int G, bool GATHER, bool VEC, int MT = 1, int R4 = 0>
 __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64_t ld, int64_t d,
                                                  int64_t ncols, const int32_t* __restrict__ idx,
                                                  const double* __restrict__ M, int NSM,
                                                  const double* __restrict__ scale,
                                                  double* __restrict__ out, int PC) {
+  constexpr int R4A = R4 > 0 ? R4 : 1;
   __shared__ double red[MT * NTW * 256];
   __shared__ double slots[MT == 1 ? NW * NTW * 256 : 1];
+  __shared__ double red4[R4 > 0 ? MT * R4 * 64 : 1];
   const int t = threadIdx.x, wave = t / 64, l = t % 64;
   const int li = l % 16, q = l / 16;
   const int64_t tile = blockIdx.x;
@@ -517,6 +533,10 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
   v4d acc[MT * NTW];
 #pragma unroll
   for (int a = 0; a < MT * NTW; ++a) acc[a] = v4d{0.0, 0.0, 0.0, 0.0};
+  double acc4[MT * R4A];
+#pragma unroll
+  for (int a = 0; a < MT * R4A; ++a) acc4[a] = 0.0;
+  const int l4 = 16 * q + (l & 3);   // lane of the tile that holds this lane's 4x4x4 B values
   const int64_t nblk = (d + 15) / 16, nfull = d / 16;
   const int64_t bpw = (nblk + NW - 1) / NW;
   const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
@@ -524,6 +544,7 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
   struct Stage {
     Raw4<TX> x[G][MT];
     double m[G][NTW][4];
+    double m4[G][R4A][4];
   };
   auto load = [&](Stage& S, int64_t g) {
 #pragma unroll
@@ -534,6 +555,8 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
       for (int mt = 0; mt < MT; ++mt) load4full<TX, VEC>(xcol[mt], r, S.x[i][mt]);
 #pragma unroll
       for (int u = 0; u < NTW; ++u) load_tile_b(M + (blk * NS + sl[u]) * 256, l, S.m[i][u]);
+#pragma unroll
+      for (int g = 0; g < R4; ++g) load_tile_b(M + (blk * NS + NTW) * 256, l4 + 4 * g, S.m4[i][g]);
     }
   };
   auto compute = [&](const Stage& S, int64_t g) {
@@ -547,6 +570,13 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt)
             acc[mt * NTW + u] = mfma_f64(S.x[i][mt].get(s), S.m[i][u][s], acc[mt * NTW + u]);
+#pragma unroll
+      for (int g = 0; g < R4; ++g)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            acc4[mt * R4A + g] = mfma_f64_4(S.x[i][mt].get(s), S.m4[i][g][s], acc4[mt * R4A + g]);
     }
   };
   if (b0 < bend) {
@@ -569,18 +599,49 @@ __global__ __launch_bounds__(NW * 64) void k_xtm(const TX* __restrict__ X, int64
     for (int mt = 0; mt < MT; ++mt) load4tail<TX>(xcol[mt], r, d, x[mt]);
 #pragma unroll
     for (int u = 0; u < NTW; ++u) load_tile_b(M + (nfull * NS + sl[u]) * 256, l, m[u]);
+    double m4[R4A][4];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int g = 0; g < R4; ++g) load_tile_b(M + (nfull * NS + NTW) * 256, l4 + 4 * g, m4[g]);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
       for (int u = 0; u < NTW; ++u)
 #pragma unroll
         for (int s = 0; s < 4; ++s)
           acc[mt * NTW + u] = mfma_f64(x[mt].get(s), m[u][s], acc[mt * NTW + u]);
+#pragma unroll
+      for (int g = 0; g < R4; ++g)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          acc4[mt * R4A + g] = mfma_f64_4(x[mt].get(s), m4[g][s], acc4[mt * R4A + g]);
+    }
   }
   if constexpr (MT == 1)
     waves_to_lds<NW, NTW>(red, slots, acc, q, li);
   else
     waves_to_lds_seq<NW, MT * NTW>(red, acc, q, li);
+  if constexpr (R4 > 0) {   // the 4x4x4 results, summed one wave at a time in wave order
+    for (int w = 0; w < NW; ++w) {
+      if (wave == w) {
+#pragma unroll
+        for (int a = 0; a < MT * R4; ++a)
+          red4[a * 64 + l] = (w == 0 ? 0.0 : red4[a * 64 + l]) + acc4[a];
+      }
+      __syncthreads();
+    }
+    // lane ll holds row 4 ((ll % 16) / 4) + ll / 16 of the tile, column 4 g + ll % 4
+    for (int e = t; e < MT * R4 * 64; e += NW * 64) {
+      const int a = e / 64, mt = a / R4, g = a % R4, ll = e % 64;
+      const int64_t cc = (tile * MT + mt) * 16 + 4 * ((ll % 16) / 4) + ll / 16;
+      const int j = NTW * 16 + 4 * g + (ll & 3);
+      if (cc < ncols && j < PC) out[cc * PC + j] = red4[e];
+    }
+    const int jz = NTW * 16 + 4 * R4, nz = PC - jz;   // padding columns
+    for (int e = t; e < MT * 16 * nz; e += NW * 64) {
+      const int64_t cc = tile * MT * 16 + e / nz;
+      if (cc < ncols) out[cc * PC + jz + e % nz] = 0.0;
+    }
+  }
   // gathered: rows from ncols up to the next multiple of 16 are written as
   // zeros (the inner-step update reads whole 16-sample blocks)
   const int64_t nrows = GATHER ? (ncols + 15) / 16 * 16 : ncols;
@@ -620,12 +681,15 @@ __device__ __forceinline__ void load4clamp(const TX* __restrict__ col, int64_t r
 // read its last block and skip their matrix-core work on a wave-uniform
 // branch).  The grid is remapped so that the row tiles of one split run on one
 // XCD (workgroups go to the 8 XCDs in turn) and share its T rows in one L2.
-template <typename TX, int NT, int G, bool VEC>
+// R4 > 0: after the NT full slices, 4 R4 more columns of T are done with
+// 4x4x4 matrix cores instead of a whole padded 16-column slice.
+template <typename TX, int NT, int G, bool VEC, int R4 = 0>
 __global__ __launch_bounds__(512) void k_xt_part(const TX* __restrict__ X, int64_t ld, int64_t d,
                                                  int64_t n, const double* __restrict__ T, int PC,
                                                  int p, double* __restrict__ part, int64_t kper) {
-  constexpr int NW = 8, MTL = 4;
+  constexpr int NW = 8, MTL = 4, R4A = R4 > 0 ? R4 : 1;
   __shared__ double red[MTL * NT * 256];
+  __shared__ double red4[R4 > 0 ? MTL * R4 * 64 : 1];
   const int t = threadIdx.x, wave = t / 64, l = t % 64;
   const int lm = l % 16, q = l / 16;
   const int RT = gridDim.x, NSP = gridDim.y;
@@ -643,16 +707,22 @@ __global__ __launch_bounds__(512) void k_xt_part(const TX* __restrict__ X, int64
   v4d acc[MTL * NT];
 #pragma unroll
   for (int a = 0; a < MTL * NT; ++a) acc[a] = v4d{0.0, 0.0, 0.0, 0.0};
+  double acc4[MTL * R4A];
+#pragma unroll
+  for (int a = 0; a < MTL * R4A; ++a) acc4[a] = 0.0;
   const int64_t nblk = ke > ks ? (ke - ks + 15) / 16 : 0;
   const int64_t nfull = ke > ks ? (ke - ks) / 16 : 0;
   const int64_t bpw = (nblk + NW - 1) / NW;
   const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
   const int64_t bend = min(b1, nfull);
   const double* __restrict__ tq = T + (ks + 4 * q) * PC + lm;
+  // this lane's column of T for the 4x4x4 groups (lane 16 k + 4 blk + n holds column n)
+  const double* __restrict__ tq4 = T + (ks + 4 * q) * PC + NT * 16 + (l & 3);
   const TX* __restrict__ xq = X + (ks + 4 * q) * ld;
   struct Stage {
     Raw4<TX> x[G][4];
     double nv[G][4][NT];
+    double nv4[G][4][R4A];
   };
   auto compute = [&](const Stage& S, int64_t g) {
 #pragma unroll
@@ -661,10 +731,14 @@ __global__ __launch_bounds__(512) void k_xt_part(const TX* __restrict__ X, int64
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int mt = 0; mt < MTL; ++mt)
+        for (int mt = 0; mt < MTL; ++mt) {
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt)
             acc[mt * NT + nt] = mfma_f64(S.x[i][s].get(mt), S.nv[i][s][nt], acc[mt * NT + nt]);
+#pragma unroll
+          for (int g = 0; g < R4; ++g)
+            acc4[mt * R4A + g] = mfma_f64_4(S.x[i][s].get(mt), S.nv4[i][s][g], acc4[mt * R4A + g]);
+        }
     }
   };
   // the ragged last row tile loads row by row with clamped rows; the others
@@ -684,6 +758,8 @@ __global__ __launch_bounds__(512) void k_xt_part(const TX* __restrict__ X, int64
             load4full<TX, VEC>(col, rbase, S.x[i][s]);
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) S.nv[i][s][nt] = tq[(blk * 16 + s) * PC + nt * 16];
+#pragma unroll
+          for (int g = 0; g < R4; ++g) S.nv4[i][s][g] = tq4[(blk * 16 + s) * PC + 4 * g];
         }
       }
     };
@@ -706,7 +782,7 @@ __global__ __launch_bounds__(512) void k_xt_part(const TX* __restrict__ X, int64
     run(std::false_type{});
   if (nfull < nblk && b0 <= nfull && nfull < b1) {   // the partial last block of columns
     Raw4<TX> x[4];
-    double nv[4][NT];
+    double nv[4][NT], nv4[4][R4A];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int64_t kc = ks + nfull * 16 + 4 * q + s;
@@ -718,14 +794,23 @@ __global__ __launch_bounds__(512) void k_xt_part(const TX* __restrict__ X, int64
         const double v = T[kcc * PC + nt * 16 + lm];
         nv[s][nt] = kv ? v : 0.0;
       }
+#pragma unroll
+      for (int g = 0; g < R4; ++g) {
+        const double v = T[kcc * PC + NT * 16 + 4 * g + (l & 3)];
+        nv4[s][g] = kv ? v : 0.0;
+      }
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int mt = 0; mt < MTL; ++mt)
+      for (int mt = 0; mt < MTL; ++mt) {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
           acc[mt * NT + nt] = mfma_f64(x[s].get(mt), nv[s][nt], acc[mt * NT + nt]);
+#pragma unroll
+        for (int g = 0; g < R4; ++g)
+          acc4[mt * R4A + g] = mfma_f64_4(x[s].get(mt), nv4[s][g], acc4[mt * R4A + g]);
+      }
   }
   waves_to_lds_seq<NW, MTL * NT>(red, acc, q, lm);
   for (int e = t; e < MTL * NT * 256; e += NW * 64) {
@@ -733,6 +818,23 @@ __global__ __launch_bounds__(512) void k_xt_part(const TX* __restrict__ X, int64
     const int64_t r = r0 + 4 * i + mt;
     const int j = nt * 16 + jj;
     if (r < d && j < p) part[(int64_t)split * p * d + (int64_t)j * d + r] = red[e];
+  }
+  if constexpr (R4 > 0) {   // the 4x4x4 results, summed one wave at a time in wave order
+    for (int w = 0; w < NW; ++w) {
+      if (wave == w) {
+#pragma unroll
+        for (int a = 0; a < MTL * R4; ++a)
+          red4[a * 64 + l] = (w == 0 ? 0.0 : red4[a * 64 + l]) + acc4[a];
+      }
+      __syncthreads();
+    }
+    // lane ll holds row 4 ((ll % 16) / 4) + ll / 16 of tile mt, column 4 g + ll % 4
+    for (int e = t; e < MTL * R4 * 64; e += NW * 64) {
+      const int a = e / 64, mt = a / R4, g = a % R4, ll = e % 64;
+      const int64_t r = r0 + 4 * (4 * ((ll % 16) / 4) + ll / 16) + mt;
+      const int j = NT * 16 + 4 * g + (ll & 3);
+      if (r < d && j < p) part[(int64_t)split * p * d + (int64_t)j * d + r] = red4[e];
+    }
   }
 }
 
@@ -1453,20 +1555,21 @@ int pass_nsplit(int64_t d, int64_t n) {
   return (int)clampi((2048 + tiles - 1) / tiles, 1, std::max<int64_t>(1, (n + 127) / 128));
 }
 
-template <int NW, int NTW, int G, bool GATHER, int MT = 1>
+template <int NW, int NTW, int G, bool GATHER, int MT = 1, int R4 = 0>
 static hipError_t launch_xtm(const XView& X, int64_t ncols, const int32_t* idx, const double* M,
                              int p, const double* scale, double* out, int PC, hipStream_t st,
                              const Probe& pr) {
   if ((uintptr_t)M % 16) return hipErrorInvalidValue;   // tile loads are 16-byte vectors
   const bool vec = x_vec_ok(X);
   const int nt = (p + 15) / 16;   // slices of M's tile layout
-  dim3 grid((unsigned)((ncols + 16 * MT - 1) / (16 * MT)), (unsigned)((nt + NTW - 1) / NTW));
+  dim3 grid((unsigned)((ncols + 16 * MT - 1) / (16 * MT)),
+            R4 > 0 ? 1u : (unsigned)((nt + NTW - 1) / NTW));
   LR_DISPATCH_DT(X.dt, TX, {
     if (vec)
-      launch(k_xtm<TX, NW, NTW, G, GATHER, true, MT>, grid, dim3(NW * 64), st, pr,
+      launch(k_xtm<TX, NW, NTW, G, GATHER, true, MT, R4>, grid, dim3(NW * 64), st, pr,
              (const TX*)X.v, X.ld, X.d, ncols, idx, M, nt, scale, out, PC);
     else
-      launch(k_xtm<TX, NW, NTW, G, GATHER, false, MT>, grid, dim3(NW * 64), st, pr,
+      launch(k_xtm<TX, NW, NTW, G, GATHER, false, MT, R4>, grid, dim3(NW * 64), st, pr,
              (const TX*)X.v, X.ld, X.d, ncols, idx, M, nt, scale, out, PC);
   });
   return hipGetLastError();
@@ -1481,11 +1584,19 @@ hipError_t pass_xtw(const XView& X, const double* W, int p, double* T, int PC, d
   const int PCw = pad16(p);
   const int64_t cnt = (X.d + 15) / 16 * 16 * PCw;
   k_cm_to_tile<<<nblocks(cnt), NT, 0, st>>>(W, X.d, p, PCw / 16, Wtile, cnt);
-  if (p > 32)
-    return launch_xtm<8, 4, 1, false, 2>(X, X.n, nullptr, Wtile, p, nullptr, T, PC, st, pr);
-  if (p > 16)
-    return launch_xtm<8, 2, 1, false, 4>(X, X.n, nullptr, Wtile, p, nullptr, T, PC, st, pr);
-  return launch_xtm<8, 1, 2, false, 4>(X, X.n, nullptr, Wtile, p, nullptr, T, PC, st, pr);
+  // whole 16-column slices, and the last p % 16 <= 12 columns as 4x4x4 groups
+  const int rem = p % 16, r4 = rem > 0 && rem <= 12 && p > 16 ? (rem + 3) / 4 : 0;
+  const int full = r4 > 0 ? p / 16 : (p + 15) / 16;
+#define LR_PASS1(NF, R)                                                                     \
+  if (full == NF && r4 == R)                                                                \
+    return launch_xtm<8, NF, (NF == 1 && R == 0 ? 2 : 1), false,                          \
+                      (NF == 1 || (NF == 2 && R == 0) ? 4 : 2), R>(                          \
+        X, X.n, nullptr, Wtile, p, nullptr, T, PC, st, pr);
+  LR_PASS1(1, 0) LR_PASS1(1, 1) LR_PASS1(1, 2) LR_PASS1(1, 3)
+  LR_PASS1(2, 0) LR_PASS1(2, 1) LR_PASS1(2, 2) LR_PASS1(2, 3)
+  LR_PASS1(3, 0) LR_PASS1(3, 1) LR_PASS1(3, 2) LR_PASS1(3, 3) LR_PASS1(4, 0)
+#undef LR_PASS1
+  return hipErrorInvalidValue;
 }
 
 hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBufs& pb,
@@ -1496,14 +1607,27 @@ hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBuf
   // columns per split: a multiple of 16, so only the last block can be partial
   const int64_t kper = ((X.n + pb.nsplit - 1) / pb.nsplit + 15) / 16 * 16;
   const bool vec = x_vec_ok(X);
-  LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV, {
-    if (vec)
-      launch(k_xt_part<TX, NTV, 1, true>, grid, dim3(512), st, pr, (const TX*)X.v, X.ld, X.d,
-             X.n, T, PC, p, pb.Ypart, kper);
-    else
-      launch(k_xt_part<TX, NTV, 1, false>, grid, dim3(512), st, pr, (const TX*)X.v, X.ld, X.d,
-             X.n, T, PC, p, pb.Ypart, kper);
-  }));
+  // whole 16-column slices, and the last p % 16 <= 12 columns as 4x4x4 groups
+  const int rem = p % 16, r4 = rem > 0 && rem <= 12 && p > 16 ? (rem + 3) / 4 : 0;
+  const int full = r4 > 0 ? p / 16 : (p + 15) / 16;
+  bool done = false;
+#define LR_PASS2(NF, R)                                                                      \
+  if (!done && full == NF && r4 == R) {                                                      \
+    done = true;                                                                             \
+    LR_DISPATCH_DT(X.dt, TX, {                                                               \
+      if (vec)                                                                               \
+        launch(k_xt_part<TX, NF, 1, true, R>, grid, dim3(512), st, pr, (const TX*)X.v, X.ld, \
+               X.d, X.n, T, PC, p, pb.Ypart, kper);                                          \
+      else                                                                                   \
+        launch(k_xt_part<TX, NF, 1, false, R>, grid, dim3(512), st, pr, (const TX*)X.v,      \
+               X.ld, X.d, X.n, T, PC, p, pb.Ypart, kper);                                    \
+    });                                                                                      \
+  }
+  LR_PASS2(1, 0) LR_PASS2(1, 1) LR_PASS2(1, 2) LR_PASS2(1, 3)
+  LR_PASS2(2, 0) LR_PASS2(2, 1) LR_PASS2(2, 2) LR_PASS2(2, 3)
+  LR_PASS2(3, 0) LR_PASS2(3, 1) LR_PASS2(3, 2) LR_PASS2(3, 3) LR_PASS2(4, 0)
+#undef LR_PASS2
+  if (!done) return hipErrorInvalidValue;
   const int64_t cnt = X.d * p;
   k_reduce_y<<<nblocks(cnt), NT, 0, st>>>(pb.Ypart, pb.nsplit, cnt, alpha, A, beta, B, gamma, out);
   return hipGetLastError();
