@@ -76,9 +76,17 @@ def test_sampling_table_and_indices_bit_exact(torch_cuda, storage):
         assert 17 not in set(idx.cpu().numpy().tolist())
 
 
+# p covers every split of the pass into whole 16-column slices plus 0..3
+# groups of four columns on 4x4x4 matrix cores: (1,0) 5, 8; (1,1) 20;
+# (1,2) 24; (1,3) 28; (2,0) 31; (2,1) 33; (2,2) 37; (2,3) 44; (3,0) 48;
+# (3,1) 51; (3,2) 55; (3,3) 60; (4,0) 64
 @pytest.mark.parametrize("storage,d,n,p", [("f64", 256, 2048, 8), ("f32", 333, 4097, 20),
                                            ("bf16", 520, 3001, 48), ("f32", 130, 999, 64),
-                                           ("f64", 77, 300, 5)])
+                                           ("f64", 77, 300, 5), ("f32", 200, 1500, 24),
+                                           ("bf16", 180, 1234, 28), ("f64", 150, 999, 31),
+                                           ("f32", 260, 2001, 33), ("f64", 97, 700, 37),
+                                           ("bf16", 300, 1700, 44), ("f32", 140, 900, 51),
+                                           ("f64", 111, 800, 55), ("f32", 333, 1900, 60)])
 def test_apply_A(torch_cuda, storage, d, n, p):
     torch = torch_cuda
     xt = random_x(d, n, storage, 3)
