@@ -54,7 +54,8 @@ def parse():
     ap.add_argument("--sparse-steps", type=int, default=200,
                     help="sparse/steps: inner steps timed (one epoch of this length)")
     ap.add_argument("--precision", type=int, default=0,
-                    help="0: FP64 arithmetic; 1: BF16 matrix-core inner steps (BF16 X)")
+                    help="0: FP64 arithmetic; 1: BF16 matrix-core inner steps (BF16 X); "
+                         "2: FP32 matrix-core inner steps (FP32 or BF16 X)")
     ap.add_argument("--batch", type=int, default=0, help="steps: minibatch size (0: 4096)")
     ap.add_argument("--adaptive", type=int, default=0,
                     help="solve: 1 = adaptive partitioning of Algorithm main")
@@ -144,8 +145,9 @@ def cpu_baseline(Xt_dev, w, sched, rep):
 def variant_leg(Xt, w, U_qk, args, name, **kw):
     """The same workload through a variant of the method (kw: adaptive = 1 for
     the adaptive partitioning of Algorithm main, accel = 1 for the accelerated
-    inner solver): solves/s, what it did, and the principal-angle sine between
-    its U_k and the plain q = k branch's."""
+    inner solver, precision = 2 for FP32 matrix-core inner steps): solves/s,
+    what it did, and the principal-angle sine between its U_k and the plain
+    q = k branch's."""
     import torch
     from paper_1607_02925_amd import lowrank
     plan = lowrank.Plan(Xt, w["k"], w["p"], w["eps"], seed=w["solver_seed"], **kw)
@@ -396,7 +398,7 @@ def main():
         return
 
     plan = lowrank.Plan(Xt, k, p, w["eps"], seed=w["solver_seed"], timing=1,
-                        adaptive=args.adaptive, accel=args.accel)
+                        adaptive=args.adaptive, accel=args.accel, precision=args.precision)
 
     if args.mode == "pass":
         Wm = torch.randn((p, d), dtype=torch.float64, device=dev).T
@@ -481,7 +483,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == 0 else "f64+f32-steps" if args.precision == 2
+                 else "f64+bf16-steps",
         "data": "synthetic planted-spectrum matrix generated on the GPU from fixed seeds",
         "config": {"workload": args.workload, "d": d, "n": n, "k": k, "p": p, "eps": w["eps"],
                    "storage": w["storage"], "form": "per-request",
@@ -501,13 +504,16 @@ def main():
                      "bytes_per_launch": dbytes, "avg_launch_ms": dms},
         "cpu_baseline": None,
     }
-    if args.adaptive or args.accel:
-        out["config"]["variant"] = {"adaptive": args.adaptive, "accel": args.accel}
+    if args.adaptive or args.accel or args.precision:
+        out["config"]["variant"] = {"adaptive": args.adaptive, "accel": args.accel,
+                                    "precision": args.precision}
     elif not args.no_variants:
         out["adaptive"] = variant_leg(Xt, w, U, args, "adaptive", adaptive=1)
         out["accel"] = variant_leg(Xt, w, U, args, "accel", accel=1)
         out["adaptive_accel"] = variant_leg(Xt, w, U, args, "adaptive+accel", adaptive=1,
                                             accel=1)
+        if Xt.dtype != torch.float64:
+            out["f32_steps"] = variant_leg(Xt, w, U, args, "f32-steps", precision=2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Xt, dict(w, **data), sched, rep)
     if not args.no_serve:

@@ -133,6 +133,13 @@ typedef struct lr_schedule {
  *                   estimates stay FP64, so each inner solve is refined against
  *                   exactly computed residuals.  Results agree with the FP64
  *                   form to the accuracy of the solve, not bit for bit.
+ *                   LR_PREC_F32_STEPS (dense FP32 or BF16 X only, else
+ *                   LR_EINVAL): the inner minibatch steps run on FP32 matrix
+ *                   cores (FP32 products, FP32 accumulation within a wave, FP64
+ *                   between waves) on FP32 copies of the step difference and of
+ *                   the sampled products; the difference itself is kept and
+ *                   updated in FP64, and everything outside the steps stays FP64
+ *                   as above.  Same agreement as the BF16 form.
  *   adaptive        0 (default): the q = k branch of Algorithm "main" (one
  *                   shift-and-invert iteration with oversampling).  1: the
  *                   adaptive partitioning of Algorithm "main" (Section 3.2):
@@ -156,7 +163,7 @@ typedef struct lr_schedule {
  *                   an epoch; a solve may take max_epochs ceil(1 / sqrt(q))
  *                   of them, q = mu / (mu + kappa).  0 (default): plain SVRG
  *                   epochs.  Not with a replay schedule. */
-typedef enum { LR_PREC_F64 = 0, LR_PREC_BF16_STEPS = 1 } lr_precision;
+typedef enum { LR_PREC_F64 = 0, LR_PREC_BF16_STEPS = 1, LR_PREC_F32_STEPS = 2 } lr_precision;
 
 typedef struct lr_options {
   uint64_t seed;

@@ -17,6 +17,7 @@
 
 #include "engine.h"
 #include "bf16.h"
+#include "f32steps.h"
 #include "kernels.h"
 #include "sparse.h"
 
@@ -70,6 +71,10 @@ struct lr_plan_s {
   // and of the sampled products (PC x ldC)
   bool bf16_steps = false;
   int64_t ldD = 0, ldC = 0;
+  // FP32 matrix-core inner steps: FP32 tile copies of the difference block
+  // (pad16(d) x PC) and of the sampled products (pad16(bmax) x PC)
+  bool f32_steps = false;
+  float *D32 = nullptr, *C32 = nullptr;
   // adaptive partitioning (Algorithm "main"): the deflation basis Ud (d x ns),
   // Z = X^T Ud (n x pad16(ns) row-major), projection temporaries, the chunk
   // partials of the deflated inner step
@@ -326,6 +331,7 @@ struct lr_plan_s {
           LR_HIP(hipMemsetAsync(Dh, 0, ldD * PC * sizeof(uint16_t), st));
           LR_HIP(hipMemsetAsync(Dlo, 0, ldD * PC * sizeof(uint16_t), st));
         }
+        if (f32_steps) LR_HIP(hipMemsetAsync(D32, 0, lr::pad16(d) * PC * sizeof(float), st));
       }
       if (opt.timing) LR_HIP(hipEventRecord(ev[0], st));
       const int64_t tprobe = m / 2;  // one launch per epoch is timed per kernel
@@ -353,6 +359,9 @@ struct lr_plan_s {
                                      ldC, PC, st, pd));
             LR_HIP(lr::step_update_bf16(X, p, b, it, Ch, Cl, ldC, PC, G, Dl, Dh, Dlo, ldD, lam_in,
                                         eta, st, pu));
+          } else if (f32_steps) {
+            LR_HIP(lr::step_dot_f32(X, p, b, it, scale + (t - t0) * b, D32, C32, PC, st, pd));
+            LR_HIP(lr::step_update_f32(X, p, b, it, C32, PC, G, Dl, D32, lam_in, eta, st, pu));
           } else {
             LR_HIP(lr::step_dot(X, pc, b, it, scale + (t - t0) * b, Dl, C, PCn, st, pd));
             LR_HIP(lr::step_update(X, pc, b, it, C, PCn, G, Dl, lam_in, eta, st, pu, df));
@@ -859,6 +868,8 @@ size_t lr_plan_s::carve(char* base) {
   take(&Kd, adaptive ? 64 * 64 : 0);
   take(&Vp, adaptive ? (int64_t)lr::zbc_chunks(bmax) * 64 * 64 : 0);
   for (uint16_t** b : {&Ch, &Cl}) take(b, bf16_steps ? ldC * PC : 0);
+  take(&D32, f32_steps ? lr::pad16(d) * PC : 0);
+  take(&C32, f32_steps ? lr::pad16(bmax) * PC : 0);
   take(&T, n * PC);
   take(&Ypart, (int64_t)pb.nsplit * dp);
   take(&C, lr::pad16(bmax) * PC);   // zero rows past b up to a multiple of 16
@@ -993,11 +1004,14 @@ lr_status plan_check(const lr_matrix* Xm, int k, int p, double eps, const lr_opt
   if (!(eps > 0)) return fail(LR_EINVAL, "eps must be positive");
   if (opt) {
     if (opt->batch < 0 || opt->batch > 8192) return fail(LR_EINVAL, "batch must be in [0, 8192]");
-    if (opt->precision < LR_PREC_F64 || opt->precision > LR_PREC_BF16_STEPS)
+    if (opt->precision < LR_PREC_F64 || opt->precision > LR_PREC_F32_STEPS)
       return fail(LR_EINVAL, "unknown precision");
     if (opt->precision == LR_PREC_BF16_STEPS &&
         (Xm->layout != LR_DENSE_COLMAJOR || Xm->dtype != LR_BF16))
       return fail(LR_EINVAL, "BF16 matrix-core steps need dense BF16 X");
+    if (opt->precision == LR_PREC_F32_STEPS &&
+        (Xm->layout != LR_DENSE_COLMAJOR || Xm->dtype == LR_F64))
+      return fail(LR_EINVAL, "FP32 matrix-core steps need dense FP32 or BF16 X");
     if (opt->adaptive < 0 || opt->adaptive > 1) return fail(LR_EINVAL, "adaptive must be 0 or 1");
     if (opt->norm < 0 || opt->norm > 1) return fail(LR_EINVAL, "norm must be 0 or 1");
     if (opt->accel < 0 || opt->accel > 1) return fail(LR_EINVAL, "accel must be 0 or 1");
@@ -1030,6 +1044,7 @@ void plan_shape(lr_plan_s* pl, const lr_matrix* Xm, int k, int p, const lr_optio
   pl->PC = lr::pad16(p);
   pl->pb.nsplit = pl->sparse ? 0 : lr::pass_nsplit(Xm->d, Xm->n);
   pl->bf16_steps = opt && opt->precision == LR_PREC_BF16_STEPS;
+  pl->f32_steps = opt && opt->precision == LR_PREC_F32_STEPS;
   pl->adaptive = opt && opt->adaptive == 1;
   pl->accel = opt && opt->accel == 1;
   pl->ldD = lr::pad_to(Xm->d, 32);

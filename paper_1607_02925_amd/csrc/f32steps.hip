@@ -1,0 +1,308 @@
+// FP32 matrix-core inner steps (v_mfma_f32_16x16x4f32, FP32 accumulation) for
+// dense X stored in FP32 or BF16 (exact in FP32).
+//
+// The instruction multiplies a 16 x 4 A by a 4 x 16 B: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16], and receives D[4 (l / 16) + v][l % 16]
+// in accumulator v (checked on the device).  As in the FP64 kernels, lane
+// (c = l % 16, q = l / 16) of a 16-row block supplies k = 4 q + s at step s.
+//
+// FP32 copies of the step difference (Dl32) and of C (C32) are kept in 1 KB
+// tiles: for each 16-row (or 16-sample) block and 16-column slice, lane l's
+// four values (k = 4 q .. 4 q + 3 of column c) sit at floats 4 l .. 4 l + 3,
+// so a wave reads a tile as one contiguous load.  The FP64 step difference
+// stays the master: the update computes it in FP64 from the FP32-accumulated
+// product and rounds it to the FP32 tile for the next step; the passes stay
+// FP64, so each epoch restarts from an exactly computed residual.
+#include "f32steps.h"
+
+#include <hip/hip_ext.h>
+
+namespace lr {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int KS32 = 8192;   // largest minibatch; its indices are staged in LDS
+
+__device__ __forceinline__ f32x4 mfma32(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float xload(const float* p) { return *p; }
+__device__ __forceinline__ float xload(const uint16_t* p) {
+  return __uint_as_float((uint32_t)*p << 16);
+}
+
+// Float offset of (k, j) in a 1 KB-tile FP32 copy with NS 16-column slices.
+__device__ __forceinline__ int64_t t32_off(int64_t k, int j, int NS) {
+  const int w = (int)(k & 15);
+  return (((k >> 4) * NS + (j >> 4)) * 64 + (w >> 2) * 16 + (j & 15)) * 4 + (w & 3);
+}
+
+__device__ __forceinline__ float4 tile32(const float* __restrict__ base, int64_t kb, int u, int NS,
+                                         int l) {
+  return *reinterpret_cast<const float4*>(base + ((kb * NS + u) * 64 + l) * 4);
+}
+
+// Four consecutive entries of one column (rows r..r+3 < d) as FP32.
+template <typename TX, bool VEC>
+__device__ __forceinline__ float4 load4f(const TX* __restrict__ col, int64_t r) {
+  if constexpr (VEC && sizeof(TX) == 4) {
+    return *reinterpret_cast<const float4*>(col + r);
+  } else if constexpr (VEC) {
+    const uint2 a = *reinterpret_cast<const uint2*>(col + r);
+    return make_float4(__uint_as_float(a.x << 16), __uint_as_float(a.x & 0xFFFF0000u),
+                       __uint_as_float(a.y << 16), __uint_as_float(a.y & 0xFFFF0000u));
+  } else {
+    return make_float4(xload(col + r), xload(col + r + 1), xload(col + r + 2), xload(col + r + 3));
+  }
+}
+
+// The same with rows >= d read as 0 (addresses clamped to row d - 1).
+template <typename TX>
+__device__ __forceinline__ float4 load4ftail(const TX* __restrict__ col, int64_t r, int64_t d) {
+  float v[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const float x = xload(col + min(r + s, d - 1));
+    v[s] = r + s < d ? x : 0.f;
+  }
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+
+__device__ __forceinline__ float f4get(const float4& v, int s) {
+  return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
+}
+
+// Sum the NW waves' accumulators (NTW 16x16 tiles each) into red[0 .. NTW*256)
+// in wave order; element (i, j) of tile u at red[u * 256 + i * 16 + j].
+template <int NW, int NTW>
+__device__ __forceinline__ void waves_sum32(double* red, double* slots, const f32x4* acc, int q,
+                                            int c) {
+  const int t = threadIdx.x, wave = t / 64;
+  double* mine = slots + wave * (NTW * 256);
+#pragma unroll
+  for (int u = 0; u < NTW; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) mine[u * 256 + (4 * q + v) * 16 + c] = (double)acc[u][v];
+  __syncthreads();
+  for (int e = t; e < NTW * 256; e += NW * 64) {
+    double s = slots[e];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s += slots[w * (NTW * 256) + e];
+    red[e] = s;
+  }
+  __syncthreads();
+}
+
+// C32 = diag(scale) X_B^T Dl32 for 16 samples x one 16-column slice
+// (y = blockIdx.y); the NW waves split the rows.  Two register stages of G
+// 16-row blocks; every load reads an in-bounds address (samples past b read
+// column idx[0] and are written as zero rows, a stage's overhang re-reads the
+// wave's last block and skips its matrix-core work on a wave-uniform branch,
+// and the partial last row block is done on its own with clamped, zeroed X
+// loads; the tiles of Dl32 hold zeros past d).
+template <typename TX, int NW, int G, bool VEC>
+__global__ __launch_bounds__(NW * 64) void k_sdot_f32(const TX* __restrict__ X, int64_t ld,
+                                                      int64_t d, int64_t b,
+                                                      const int32_t* __restrict__ idx,
+                                                      const double* __restrict__ scale,
+                                                      const float* __restrict__ D32,
+                                                      float* __restrict__ C32, int NS) {
+  __shared__ double red[256];
+  __shared__ double slots[NW * 256];
+  const int t = threadIdx.x, wave = t / 64, l = t % 64, c = l % 16, q = l / 16;
+  const int64_t s0 = (int64_t)blockIdx.x * 16;
+  const int u = blockIdx.y;
+  const TX* __restrict__ xcol = X + (int64_t)idx[s0 + c < b ? s0 + c : 0] * ld;
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int64_t nblk = (d + 15) / 16, nfull = d / 16;
+  const int64_t bpw = (nblk + NW - 1) / NW;
+  const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
+  const int64_t bend = min(b1, nfull);
+  struct Stage {
+    float4 x[G], m[G];
+  };
+  auto load = [&](Stage& S, int64_t g) {
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const int64_t blk = min(g + i, bend - 1);
+      S.x[i] = load4f<TX, VEC>(xcol, blk * 16 + 4 * q);
+      S.m[i] = tile32(D32, blk, u, NS, l);
+    }
+  };
+  auto compute = [&](const Stage& S, int64_t g) {
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      if (g + i >= bend) break;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = mfma32(f4get(S.x[i], s), f4get(S.m[i], s), acc);
+    }
+  };
+  if (b0 < bend) {
+    Stage A, B;
+    load(A, b0);
+    for (int64_t g = b0; g < bend; g += 2 * G) {
+      load(B, g + G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(A, g);
+      load(A, g + 2 * G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(B, g + G);
+    }
+  }
+  if (nfull < nblk && b0 <= nfull && nfull < b1) {   // the partial last block of rows
+    const float4 x = load4ftail<TX>(xcol, nfull * 16 + 4 * q, d);
+    const float4 m = tile32(D32, nfull, u, NS, l);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = mfma32(f4get(x, s), f4get(m, s), acc);
+  }
+  waves_sum32<NW, 1>(red, slots, &acc, q, c);
+  // rows from b up to the next multiple of 16 are written as zeros (the update
+  // reads whole 16-sample blocks)
+  if (t < 256) {
+    const int i = t / 16, j = t % 16;
+    const int64_t ss = s0 + i;
+    C32[t32_off(ss, u * 16 + j, NS)] = ss < b ? (float)(scale[ss] * red[t]) : 0.f;
+  }
+}
+
+// Dl <- Dl - eta (G + lam Dl - U), U[r, j] = sum_s X[r, idx[s]] C32[s, j], for a
+// tile of 16 rows and one 16-column slice; the new Dl (FP64, tile-major, the
+// layout of the FP64 path) is also rounded into the FP32 tile for the next
+// step.  The NW waves split the samples (indices staged in LDS, padded to a
+// multiple of 16 with a valid column; C32 holds zero rows past b); two register
+// stages; rows past d read row d - 1 (not stored).  The grid (a multiple of 8
+// tiles) is remapped so each XCD owns a contiguous run of row tiles.
+template <typename TX, int NW, int G>
+__global__ __launch_bounds__(NW * 64) void k_supd_f32(const TX* __restrict__ X, int64_t ld,
+                                                      int64_t d, int64_t b,
+                                                      const int32_t* __restrict__ idx,
+                                                      const float* __restrict__ C32, int p,
+                                                      int NS, const double* __restrict__ Gr,
+                                                      double* __restrict__ Dl,
+                                                      float* __restrict__ D32, double lam,
+                                                      double eta) {
+  __shared__ double red[256];
+  __shared__ double slots[NW * 256];
+  __shared__ int sidx[KS32];
+  const int t = threadIdx.x, wave = t / 64, l = t % 64, c = l % 16, q = l / 16;
+  const int64_t tile = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  const int64_t r0 = tile * 16;
+  if (r0 >= d) return;
+  const int u = blockIdx.y;
+  const int64_t bpad = (b + 15) / 16 * 16;
+  for (int64_t e = t; e < bpad; e += NW * 64) sidx[e] = idx[e < b ? e : 0];
+  __syncthreads();
+  const TX* __restrict__ xrow = X + min(r0 + c, d - 1);
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int64_t nblk = bpad / 16;
+  const int64_t bpw = (nblk + NW - 1) / NW;
+  const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
+  const int* __restrict__ sq = sidx + 4 * q;
+  struct Stage {
+    float x[G][4];
+    float4 m[G];
+  };
+  auto load = [&](Stage& S, int64_t g) {
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const int64_t blk = min(g + i, b1 - 1);
+      const int* __restrict__ si = sq + blk * 16;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) S.x[i][s] = xload(xrow + (int64_t)si[s] * ld);
+      S.m[i] = tile32(C32, blk, u, NS, l);
+    }
+  };
+  auto compute = [&](const Stage& S, int64_t g) {
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      if (g + i >= b1) break;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = mfma32(S.x[i][s], f4get(S.m[i], s), acc);
+    }
+  };
+  if (b0 < b1) {
+    Stage A, B;
+    load(A, b0);
+    for (int64_t g = b0; g < b1; g += 2 * G) {
+      load(B, g + G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(A, g);
+      load(A, g + 2 * G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(B, g + G);
+    }
+  }
+  waves_sum32<NW, 1>(red, slots, &acc, q, c);
+  if (t < 256) {
+    const int i = t / 16, j = u * 16 + t % 16;
+    const int64_t r = r0 + i;
+    if (r < d && j < p) {
+      // the FP64 master, tile-major as on the FP64 path
+      const int rho = (int)(r & 15), qq = rho >> 2, ss = rho & 3;
+      const int64_t o = ((r >> 4) * NS + (j >> 4)) * 256 + (ss >> 1) * 128 +
+                        (qq * 16 + (j & 15)) * 2 + (ss & 1);
+      const double x0 = Dl[o];
+      const double x = x0 - eta * (Gr[(int64_t)j * d + r] + lam * x0 - red[t]);
+      Dl[o] = x;
+      D32[t32_off(r, j, NS)] = (float)x;
+    }
+  }
+}
+
+template <typename K, typename... A>
+static void launch32(K kernel, dim3 grid, dim3 block, hipStream_t st, const Probe& pr, A... args) {
+  if (pr.start)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, pr.start, pr.stop, 0, args...);
+  else
+    kernel<<<grid, block, 0, st>>>(args...);
+}
+
+}  // namespace
+
+hipError_t step_dot_f32(const XView& X, int p, int64_t b, const int32_t* idx,
+                        const double* scale, const float* D32, float* C32, int PC,
+                        hipStream_t st, const Probe& pr) {
+  if ((X.dt != 1 && X.dt != 2) || PC % 16 || PC > 64 || p > PC || (uintptr_t)D32 % 16)
+    return hipErrorInvalidValue;
+  const bool vec = X.dt == 1 ? X.ld % 4 == 0 && (uintptr_t)X.v % 16 == 0
+                             : X.ld % 4 == 0 && (uintptr_t)X.v % 8 == 0;
+  const dim3 grid((unsigned)((b + 15) / 16), (unsigned)((p + 15) / 16));
+  const int NS = PC / 16;
+  if (X.dt == 1) {
+    if (vec)
+      launch32(k_sdot_f32<float, 8, 2, true>, grid, dim3(512), st, pr, (const float*)X.v, X.ld,
+               X.d, b, idx, scale, D32, C32, NS);
+    else
+      launch32(k_sdot_f32<float, 8, 2, false>, grid, dim3(512), st, pr, (const float*)X.v, X.ld,
+               X.d, b, idx, scale, D32, C32, NS);
+  } else {
+    if (vec)
+      launch32(k_sdot_f32<uint16_t, 8, 2, true>, grid, dim3(512), st, pr, (const uint16_t*)X.v,
+               X.ld, X.d, b, idx, scale, D32, C32, NS);
+    else
+      launch32(k_sdot_f32<uint16_t, 8, 2, false>, grid, dim3(512), st, pr, (const uint16_t*)X.v,
+               X.ld, X.d, b, idx, scale, D32, C32, NS);
+  }
+  return hipGetLastError();
+}
+
+hipError_t step_update_f32(const XView& X, int p, int64_t b, const int32_t* idx, const float* C32,
+                           int PC, const double* G, double* Dl, float* D32, double lam,
+                           double eta, hipStream_t st, const Probe& pr) {
+  if ((X.dt != 1 && X.dt != 2) || b > KS32 || PC % 16 || PC > 64 || p > PC ||
+      (uintptr_t)C32 % 16)
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(((X.d + 15) / 16 + 7) / 8 * 8), (unsigned)((p + 15) / 16));
+  const int NS = PC / 16;
+  if (X.dt == 1)
+    launch32(k_supd_f32<float, 16, 1>, grid, dim3(1024), st, pr, (const float*)X.v, X.ld, X.d, b,
+             idx, C32, p, NS, G, Dl, D32, lam, eta);
+  else
+    launch32(k_supd_f32<uint16_t, 16, 1>, grid, dim3(1024), st, pr, (const uint16_t*)X.v, X.ld,
+             X.d, b, idx, C32, p, NS, G, Dl, D32, lam, eta);
+  return hipGetLastError();
+}
+
+}  // namespace lr

@@ -19,7 +19,7 @@ LR_MAX_P = 64
 LR_MAX_SHIFT_ROUNDS = 64
 LR_MAX_SLOTS = 16
 LR_F64, LR_F32, LR_BF16 = 0, 1, 2
-LR_PREC_F64, LR_PREC_BF16_STEPS = 0, 1
+LR_PREC_F64, LR_PREC_BF16_STEPS, LR_PREC_F32_STEPS = 0, 1, 2
 
 
 class lr_matrix(ctypes.Structure):

@@ -102,6 +102,37 @@ def test_precision_option_checks(lib):
     assert out1.value > out0.value
 
 
+def test_f32_steps_option_checks(lib):
+    """The FP32 matrix-core steps take dense FP32 or BF16 X; their FP32 tile
+    copies (pad16(d) x 16 and pad16(b_max) x 16 floats here) add to the
+    workspace."""
+    from paper_1607_02925_amd import lowrank
+    h = ctypes.c_void_p()
+    opt = lowrank.lr_options()
+    lib.lowrank_options_default(ctypes.byref(opt))
+    opt.precision = lowrank.LR_PREC_F32_STEPS
+    m = _mat(100, 500, dtype=lowrank.LR_F64)
+    assert lib.lowrank_plan(ctypes.byref(h), ctypes.byref(m), 2, 4, 1e-4, ctypes.byref(opt),
+                            None) == lowrank.LR_EINVAL
+    assert b"FP32 matrix-core" in lib.lowrank_last_error()
+    opt.adaptive = 1
+    m = _mat(100, 500, dtype=lowrank.LR_F32)
+    assert lib.lowrank_plan(ctypes.byref(h), ctypes.byref(m), 2, 4, 1e-4, ctypes.byref(opt),
+                            None) == lowrank.LR_EINVAL
+    opt.adaptive = 0
+    for dt in (lowrank.LR_F32, lowrank.LR_BF16):
+        m = _mat(100, 500, dtype=dt)
+        out0, out2 = ctypes.c_size_t(), ctypes.c_size_t()
+        opt.precision = lowrank.LR_PREC_F64
+        assert lib.lowrank_plan_bytes(ctypes.byref(m), 2, 4, ctypes.byref(opt),
+                                      ctypes.byref(out0)) == 0
+        opt.precision = lowrank.LR_PREC_F32_STEPS
+        assert lib.lowrank_plan_bytes(ctypes.byref(m), 2, 4, ctypes.byref(opt),
+                                      ctypes.byref(out2)) == 0
+        # 112 x 16 and 512 x 16 floats, each in place of an empty 256-byte slot
+        assert out2.value - out0.value == (112 * 16 * 4 - 256) + (512 * 16 * 4 - 256)
+
+
 def test_accel_option_checks(lib):
     """accel takes 0 or 1 and does not combine with a replay schedule; the
     momentum buffers add to the workspace."""
