@@ -72,7 +72,8 @@ struct lr_plan_s {
   bool bf16_steps = false;
   int64_t ldD = 0, ldC = 0;
   // FP32 matrix-core inner steps: FP32 tile copies of the difference block
-  // (pad16(d) x PC) and of the sampled products (pad16(bmax) x PC)
+  // (pad16(d) x PC) and of the sampled products (up to 2 partial sums over row
+  // ranges, each pad16(bmax) x PC)
   bool f32_steps = false;
   float *D32 = nullptr, *C32 = nullptr;
   // adaptive partitioning (Algorithm "main"): the deflation basis Ud (d x ns),
@@ -869,7 +870,7 @@ size_t lr_plan_s::carve(char* base) {
   take(&Vp, adaptive ? (int64_t)lr::zbc_chunks(bmax) * 64 * 64 : 0);
   for (uint16_t** b : {&Ch, &Cl}) take(b, bf16_steps ? ldC * PC : 0);
   take(&D32, f32_steps ? lr::pad16(d) * PC : 0);
-  take(&C32, f32_steps ? lr::pad16(bmax) * PC : 0);
+  take(&C32, f32_steps ? 2 * lr::pad16(bmax) * PC : 0);   // two row-split partials
   take(&T, n * PC);
   take(&Ypart, (int64_t)pb.nsplit * dp);
   take(&C, lr::pad16(bmax) * PC);   // zero rows past b up to a multiple of 16

@@ -74,61 +74,75 @@ __device__ __forceinline__ float f4get(const float4& v, int s) {
   return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
 }
 
-// Sum the NW waves' accumulators (NTW 16x16 tiles each) into red[0 .. NTW*256)
-// in wave order; element (i, j) of tile u at red[u * 256 + i * 16 + j].
-template <int NW, int NTW>
+// Sum the NW waves' accumulators (NT 16x16 tiles each) into red[0 .. NT*256)
+// in wave order, one tile at a time through NW*256 slots; element (i, j) of
+// tile u lands at red[u * 256 + i * 16 + j].
+template <int NW, int NT>
 __device__ __forceinline__ void waves_sum32(double* red, double* slots, const f32x4* acc, int q,
                                             int c) {
   const int t = threadIdx.x, wave = t / 64;
-  double* mine = slots + wave * (NTW * 256);
+  double* mine = slots + wave * 256;
 #pragma unroll
-  for (int u = 0; u < NTW; ++u)
+  for (int u = 0; u < NT; ++u) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) mine[u * 256 + (4 * q + v) * 16 + c] = (double)acc[u][v];
-  __syncthreads();
-  for (int e = t; e < NTW * 256; e += NW * 64) {
-    double s = slots[e];
+    for (int v = 0; v < 4; ++v) mine[(4 * q + v) * 16 + c] = (double)acc[u][v];
+    __syncthreads();
+    for (int e = t; e < 256; e += NW * 64) {
+      double s = slots[e];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) s += slots[w * (NTW * 256) + e];
-    red[e] = s;
+      for (int w = 1; w < NW; ++w) s += slots[w * 256 + e];
+      red[u * 256 + e] = s;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
-// C32 = diag(scale) X_B^T Dl32 for 16 samples x one 16-column slice
-// (y = blockIdx.y); the NW waves split the rows.  Two register stages of G
-// 16-row blocks; every load reads an in-bounds address (samples past b read
-// column idx[0] and are written as zero rows, a stage's overhang re-reads the
-// wave's last block and skips its matrix-core work on a wave-uniform branch,
-// and the partial last row block is done on its own with clamped, zeroed X
-// loads; the tiles of Dl32 hold zeros past d).
-template <typename TX, int NW, int G, bool VEC>
+// Number of row splits of the sample dot: 2 below 256 blocks of 16 samples,
+// so the workgroups cover more of the 256 compute units, else 1.  (Four splits
+// cost the update more than they save the dot at every size measured.)
+inline int dot_splits(int64_t b) { return (b + 15) / 16 >= 256 ? 1 : 2; }
+
+// Partial C32 for 16 samples x all NT = PC / 16 column slices over the rows of
+// split z = blockIdx.z (a run of bps 16-row blocks, possibly empty):
+// C32p_z = diag(scale) X_B^T D32 restricted to those rows, at C32 + z cstride.
+// One X load serves all slices.  The NW waves split the split's row blocks.
+// Two register stages of G 16-row blocks; every load reads an in-bounds
+// address (samples past b read column idx[0] and are written as zero rows, a
+// stage's overhang re-reads the wave's last block and skips its matrix-core
+// work on a wave-uniform branch, and the partial last row block is done on its
+// own with clamped, zeroed X loads; the tiles of D32 hold zeros past d).
+template <typename TX, int NW, int G, bool VEC, int NT>
 __global__ __launch_bounds__(NW * 64) void k_sdot_f32(const TX* __restrict__ X, int64_t ld,
                                                       int64_t d, int64_t b,
                                                       const int32_t* __restrict__ idx,
                                                       const double* __restrict__ scale,
                                                       const float* __restrict__ D32,
-                                                      float* __restrict__ C32, int NS) {
-  __shared__ double red[256];
+                                                      float* __restrict__ C32, int64_t bps,
+                                                      int64_t cstride) {
+  __shared__ double red[NT * 256];
   __shared__ double slots[NW * 256];
   const int t = threadIdx.x, wave = t / 64, l = t % 64, c = l % 16, q = l / 16;
   const int64_t s0 = (int64_t)blockIdx.x * 16;
-  const int u = blockIdx.y;
   const TX* __restrict__ xcol = X + (int64_t)idx[s0 + c < b ? s0 + c : 0] * ld;
-  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[NT];
+#pragma unroll
+  for (int v = 0; v < NT; ++v) acc[v] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int64_t nblk = (d + 15) / 16, nfull = d / 16;
-  const int64_t bpw = (nblk + NW - 1) / NW;
-  const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
+  const int64_t k0 = min(nblk, (int64_t)blockIdx.z * bps), k1 = min(nblk, k0 + bps);
+  const int64_t bpw = (k1 - k0 + NW - 1) / NW;
+  const int64_t b0 = k0 + wave * bpw, b1 = min(k1, b0 + bpw);
   const int64_t bend = min(b1, nfull);
   struct Stage {
-    float4 x[G], m[G];
+    float4 x[G];
+    float4 m[G][NT];
   };
   auto load = [&](Stage& S, int64_t g) {
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       const int64_t blk = min(g + i, bend - 1);
       S.x[i] = load4f<TX, VEC>(xcol, blk * 16 + 4 * q);
-      S.m[i] = tile32(D32, blk, u, NS, l);
+#pragma unroll
+      for (int v = 0; v < NT; ++v) S.m[i][v] = tile32(D32, blk, v, NT, l);
     }
   };
   auto compute = [&](const Stage& S, int64_t g) {
@@ -136,7 +150,10 @@ __global__ __launch_bounds__(NW * 64) void k_sdot_f32(const TX* __restrict__ X, 
     for (int i = 0; i < G; ++i) {
       if (g + i >= bend) break;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc = mfma32(f4get(S.x[i], s), f4get(S.m[i], s), acc);
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int v = 0; v < NT; ++v)
+          acc[v] = mfma32(f4get(S.x[i], s), f4get(S.m[i][v], s), acc[v]);
     }
   };
   if (b0 < bend) {
@@ -153,56 +170,65 @@ __global__ __launch_bounds__(NW * 64) void k_sdot_f32(const TX* __restrict__ X, 
   }
   if (nfull < nblk && b0 <= nfull && nfull < b1) {   // the partial last block of rows
     const float4 x = load4ftail<TX>(xcol, nfull * 16 + 4 * q, d);
-    const float4 m = tile32(D32, nfull, u, NS, l);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc = mfma32(f4get(x, s), f4get(m, s), acc);
+    for (int v = 0; v < NT; ++v) {
+      const float4 m = tile32(D32, nfull, v, NT, l);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[v] = mfma32(f4get(x, s), f4get(m, s), acc[v]);
+    }
   }
-  waves_sum32<NW, 1>(red, slots, &acc, q, c);
+  waves_sum32<NW, NT>(red, slots, acc, q, c);
   // rows from b up to the next multiple of 16 are written as zeros (the update
   // reads whole 16-sample blocks)
-  if (t < 256) {
-    const int i = t / 16, j = t % 16;
+  float* __restrict__ out = C32 + (int64_t)blockIdx.z * cstride;
+  for (int e = t; e < NT * 256; e += NW * 64) {
+    const int v = e / 256, i = (e % 256) / 16, j = e % 16;
     const int64_t ss = s0 + i;
-    C32[t32_off(ss, u * 16 + j, NS)] = ss < b ? (float)(scale[ss] * red[t]) : 0.f;
+    out[t32_off(ss, v * 16 + j, NT)] = ss < b ? (float)(scale[ss] * red[e]) : 0.f;
   }
 }
 
-// Dl <- Dl - eta (G + lam Dl - U), U[r, j] = sum_s X[r, idx[s]] C32[s, j], for a
-// tile of 16 rows and one 16-column slice; the new Dl (FP64, tile-major, the
-// layout of the FP64 path) is also rounded into the FP32 tile for the next
-// step.  The NW waves split the samples (indices staged in LDS, padded to a
-// multiple of 16 with a valid column; C32 holds zero rows past b); two register
-// stages; rows past d read row d - 1 (not stored).  The grid (a multiple of 8
-// tiles) is remapped so each XCD owns a contiguous run of row tiles.
-template <typename TX, int NW, int G>
+// Dl <- Dl - eta (G + lam Dl - U), U[r, j] = sum_s X[r, idx[s]] C[s, j] with C
+// the sum of the KS partial copies at C32 + z cstride, for a tile of 16 rows
+// and NT column slices starting at slice NT blockIdx.y (one X load serves
+// them all); the new Dl (FP64, tile-major, the layout of the FP64 path) is
+// also rounded into the FP32 tile for the next step.  The NW waves split the
+// samples (indices staged in LDS, padded to a multiple of 16 with a valid
+// column; C32 holds zero rows past b); two register stages; rows past d read
+// row d - 1 (not stored).  The grid (a multiple of 8 tiles) is remapped so
+// each XCD owns a contiguous run of row tiles.
+template <typename TX, int NW, int G, int NT, int KS>
 __global__ __launch_bounds__(NW * 64) void k_supd_f32(const TX* __restrict__ X, int64_t ld,
                                                       int64_t d, int64_t b,
                                                       const int32_t* __restrict__ idx,
-                                                      const float* __restrict__ C32, int p,
-                                                      int NS, const double* __restrict__ Gr,
+                                                      const float* __restrict__ C32,
+                                                      int64_t cstride, int p, int NS,
+                                                      const double* __restrict__ Gr,
                                                       double* __restrict__ Dl,
                                                       float* __restrict__ D32, double lam,
                                                       double eta) {
-  __shared__ double red[256];
+  __shared__ double red[NT * 256];
   __shared__ double slots[NW * 256];
   __shared__ int sidx[KS32];
   const int t = threadIdx.x, wave = t / 64, l = t % 64, c = l % 16, q = l / 16;
   const int64_t tile = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
   const int64_t r0 = tile * 16;
   if (r0 >= d) return;
-  const int u = blockIdx.y;
+  const int u0 = blockIdx.y * NT;
   const int64_t bpad = (b + 15) / 16 * 16;
   for (int64_t e = t; e < bpad; e += NW * 64) sidx[e] = idx[e < b ? e : 0];
   __syncthreads();
   const TX* __restrict__ xrow = X + min(r0 + c, d - 1);
-  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[NT];
+#pragma unroll
+  for (int v = 0; v < NT; ++v) acc[v] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int64_t nblk = bpad / 16;
   const int64_t bpw = (nblk + NW - 1) / NW;
   const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
   const int* __restrict__ sq = sidx + 4 * q;
   struct Stage {
     float x[G][4];
-    float4 m[G];
+    float4 m[G][NT];
   };
   auto load = [&](Stage& S, int64_t g) {
 #pragma unroll
@@ -211,7 +237,19 @@ __global__ __launch_bounds__(NW * 64) void k_supd_f32(const TX* __restrict__ X, 
       const int* __restrict__ si = sq + blk * 16;
 #pragma unroll
       for (int s = 0; s < 4; ++s) S.x[i][s] = xload(xrow + (int64_t)si[s] * ld);
-      S.m[i] = tile32(C32, blk, u, NS, l);
+#pragma unroll
+      for (int v = 0; v < NT; ++v) {
+        float4 m = tile32(C32, blk, u0 + v, NS, l);
+#pragma unroll
+        for (int z = 1; z < KS; ++z) {
+          const float4 y = tile32(C32 + z * cstride, blk, u0 + v, NS, l);
+          m.x += y.x;
+          m.y += y.y;
+          m.z += y.z;
+          m.w += y.w;
+        }
+        S.m[i][v] = m;
+      }
     }
   };
   auto compute = [&](const Stage& S, int64_t g) {
@@ -219,7 +257,9 @@ __global__ __launch_bounds__(NW * 64) void k_supd_f32(const TX* __restrict__ X, 
     for (int i = 0; i < G; ++i) {
       if (g + i >= b1) break;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc = mfma32(S.x[i][s], f4get(S.m[i], s), acc);
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int v = 0; v < NT; ++v) acc[v] = mfma32(S.x[i][s], f4get(S.m[i][v], s), acc[v]);
     }
   };
   if (b0 < b1) {
@@ -234,9 +274,9 @@ __global__ __launch_bounds__(NW * 64) void k_supd_f32(const TX* __restrict__ X, 
       compute(B, g + G);
     }
   }
-  waves_sum32<NW, 1>(red, slots, &acc, q, c);
-  if (t < 256) {
-    const int i = t / 16, j = u * 16 + t % 16;
+  waves_sum32<NW, NT>(red, slots, acc, q, c);
+  for (int e = t; e < NT * 256; e += NW * 64) {
+    const int i = (e % 256) / 16, j = (u0 + e / 256) * 16 + e % 16;
     const int64_t r = r0 + i;
     if (r < d && j < p) {
       // the FP64 master, tile-major as on the FP64 path
@@ -244,7 +284,7 @@ __global__ __launch_bounds__(NW * 64) void k_supd_f32(const TX* __restrict__ X, 
       const int64_t o = ((r >> 4) * NS + (j >> 4)) * 256 + (ss >> 1) * 128 +
                         (qq * 16 + (j & 15)) * 2 + (ss & 1);
       const double x0 = Dl[o];
-      const double x = x0 - eta * (Gr[(int64_t)j * d + r] + lam * x0 - red[t]);
+      const double x = x0 - eta * (Gr[(int64_t)j * d + r] + lam * x0 - red[e]);
       Dl[o] = x;
       D32[t32_off(r, j, NS)] = (float)x;
     }
@@ -259,31 +299,83 @@ static void launch32(K kernel, dim3 grid, dim3 block, hipStream_t st, const Prob
     kernel<<<grid, block, 0, st>>>(args...);
 }
 
+template <typename TX, bool VEC, int NT>
+void sdot_launch(const XView& X, int64_t b, const int32_t* idx, const double* scale,
+                 const float* D32, float* C32, hipStream_t st, const Probe& pr, int ks) {
+  const int64_t nblk = (X.d + 15) / 16;
+  const dim3 grid((unsigned)((b + 15) / 16), 1, (unsigned)ks);
+  launch32(k_sdot_f32<TX, 8, 2, VEC, NT>, grid, dim3(512), st, pr, (const TX*)X.v, X.ld, X.d, b,
+           idx, scale, D32, C32, (nblk + ks - 1) / ks, (b + 15) / 16 * 16 * (NT * 16));
+}
+
+template <typename TX, bool VEC>
+void sdot_nt(int NS, const XView& X, int64_t b, const int32_t* idx, const double* scale,
+             const float* D32, float* C32, hipStream_t st, const Probe& pr, int ks) {
+  switch (NS) {
+    case 1: sdot_launch<TX, VEC, 1>(X, b, idx, scale, D32, C32, st, pr, ks); break;
+    case 2: sdot_launch<TX, VEC, 2>(X, b, idx, scale, D32, C32, st, pr, ks); break;
+    case 3: sdot_launch<TX, VEC, 3>(X, b, idx, scale, D32, C32, st, pr, ks); break;
+    default: sdot_launch<TX, VEC, 4>(X, b, idx, scale, D32, C32, st, pr, ks); break;
+  }
+}
+
+// Row tiles of 16 from which the update takes all column slices in one
+// workgroup (fewer tiles: one slice per workgroup, so the grid still covers
+// the compute units).
+constexpr int64_t UPD_ALL_SLICES_TILES = 256;
+
+template <typename TX, int NT, int KS>
+void supd_launch(const XView& X, int p, int NS, int64_t b, const int32_t* idx, const float* C32,
+                 const double* G, double* Dl, float* D32, double lam, double eta, hipStream_t st,
+                 const Probe& pr) {
+  const dim3 grid((unsigned)(((X.d + 15) / 16 + 7) / 8 * 8), (unsigned)(NS / NT));
+  launch32(k_supd_f32<TX, 16, 1, NT, KS>, grid, dim3(1024), st, pr, (const TX*)X.v, X.ld, X.d, b,
+           idx, C32, (b + 15) / 16 * 16 * (NS * 16), p, NS, G, Dl, D32, lam, eta);
+}
+
+template <typename TX, int KS>
+void supd_nt(int NS, const XView& X, int p, int64_t b, const int32_t* idx, const float* C32,
+             const double* G, double* Dl, float* D32, double lam, double eta, hipStream_t st,
+             const Probe& pr) {
+  switch ((X.d + 15) / 16 >= UPD_ALL_SLICES_TILES ? NS : 1) {
+    case 2: supd_launch<TX, 2, KS>(X, p, NS, b, idx, C32, G, Dl, D32, lam, eta, st, pr); break;
+    case 3: supd_launch<TX, 3, KS>(X, p, NS, b, idx, C32, G, Dl, D32, lam, eta, st, pr); break;
+    case 4: supd_launch<TX, 4, KS>(X, p, NS, b, idx, C32, G, Dl, D32, lam, eta, st, pr); break;
+    default: supd_launch<TX, 1, KS>(X, p, NS, b, idx, C32, G, Dl, D32, lam, eta, st, pr); break;
+  }
+}
+
+template <typename TX>
+void supd_ks(int NS, const XView& X, int p, int64_t b, const int32_t* idx, const float* C32,
+             const double* G, double* Dl, float* D32, double lam, double eta, hipStream_t st,
+             const Probe& pr, int ks) {
+  if (ks == 1)
+    supd_nt<TX, 1>(NS, X, p, b, idx, C32, G, Dl, D32, lam, eta, st, pr);
+  else
+    supd_nt<TX, 2>(NS, X, p, b, idx, C32, G, Dl, D32, lam, eta, st, pr);
+}
+
 }  // namespace
 
 hipError_t step_dot_f32(const XView& X, int p, int64_t b, const int32_t* idx,
                         const double* scale, const float* D32, float* C32, int PC,
                         hipStream_t st, const Probe& pr) {
-  if ((X.dt != 1 && X.dt != 2) || PC % 16 || PC > 64 || p > PC || (uintptr_t)D32 % 16)
+  if ((X.dt != 1 && X.dt != 2) || b < 1 || PC % 16 || PC > 64 || p > PC || PC - p >= 16 ||
+      (uintptr_t)D32 % 16 || (uintptr_t)C32 % 16)
     return hipErrorInvalidValue;
   const bool vec = X.dt == 1 ? X.ld % 4 == 0 && (uintptr_t)X.v % 16 == 0
                              : X.ld % 4 == 0 && (uintptr_t)X.v % 8 == 0;
-  const dim3 grid((unsigned)((b + 15) / 16), (unsigned)((p + 15) / 16));
   const int NS = PC / 16;
   if (X.dt == 1) {
     if (vec)
-      launch32(k_sdot_f32<float, 8, 2, true>, grid, dim3(512), st, pr, (const float*)X.v, X.ld,
-               X.d, b, idx, scale, D32, C32, NS);
+      sdot_nt<float, true>(NS, X, b, idx, scale, D32, C32, st, pr, dot_splits(b));
     else
-      launch32(k_sdot_f32<float, 8, 2, false>, grid, dim3(512), st, pr, (const float*)X.v, X.ld,
-               X.d, b, idx, scale, D32, C32, NS);
+      sdot_nt<float, false>(NS, X, b, idx, scale, D32, C32, st, pr, dot_splits(b));
   } else {
     if (vec)
-      launch32(k_sdot_f32<uint16_t, 8, 2, true>, grid, dim3(512), st, pr, (const uint16_t*)X.v,
-               X.ld, X.d, b, idx, scale, D32, C32, NS);
+      sdot_nt<uint16_t, true>(NS, X, b, idx, scale, D32, C32, st, pr, dot_splits(b));
     else
-      launch32(k_sdot_f32<uint16_t, 8, 2, false>, grid, dim3(512), st, pr, (const uint16_t*)X.v,
-               X.ld, X.d, b, idx, scale, D32, C32, NS);
+      sdot_nt<uint16_t, false>(NS, X, b, idx, scale, D32, C32, st, pr, dot_splits(b));
   }
   return hipGetLastError();
 }
@@ -291,17 +383,14 @@ hipError_t step_dot_f32(const XView& X, int p, int64_t b, const int32_t* idx,
 hipError_t step_update_f32(const XView& X, int p, int64_t b, const int32_t* idx, const float* C32,
                            int PC, const double* G, double* Dl, float* D32, double lam,
                            double eta, hipStream_t st, const Probe& pr) {
-  if ((X.dt != 1 && X.dt != 2) || b > KS32 || PC % 16 || PC > 64 || p > PC ||
-      (uintptr_t)C32 % 16)
+  if ((X.dt != 1 && X.dt != 2) || b < 1 || b > KS32 || PC % 16 || PC > 64 || p > PC ||
+      PC - p >= 16 || (uintptr_t)C32 % 16)
     return hipErrorInvalidValue;
-  const dim3 grid((unsigned)(((X.d + 15) / 16 + 7) / 8 * 8), (unsigned)((p + 15) / 16));
   const int NS = PC / 16;
   if (X.dt == 1)
-    launch32(k_supd_f32<float, 16, 1>, grid, dim3(1024), st, pr, (const float*)X.v, X.ld, X.d, b,
-             idx, C32, p, NS, G, Dl, D32, lam, eta);
+    supd_ks<float>(NS, X, p, b, idx, C32, G, Dl, D32, lam, eta, st, pr, dot_splits(b));
   else
-    launch32(k_supd_f32<uint16_t, 16, 1>, grid, dim3(1024), st, pr, (const uint16_t*)X.v, X.ld,
-             X.d, b, idx, C32, p, NS, G, Dl, D32, lam, eta);
+    supd_ks<uint16_t>(NS, X, p, b, idx, C32, G, Dl, D32, lam, eta, st, pr, dot_splits(b));
   return hipGetLastError();
 }
 

@@ -104,8 +104,8 @@ def test_precision_option_checks(lib):
 
 def test_f32_steps_option_checks(lib):
     """The FP32 matrix-core steps take dense FP32 or BF16 X; their FP32 tile
-    copies (pad16(d) x 16 and pad16(b_max) x 16 floats here) add to the
-    workspace."""
+    copies (pad16(d) x 16 floats and two pad16(b_max) x 16 partials here) add
+    to the workspace."""
     from paper_1607_02925_amd import lowrank
     h = ctypes.c_void_p()
     opt = lowrank.lr_options()
@@ -129,8 +129,8 @@ def test_f32_steps_option_checks(lib):
         opt.precision = lowrank.LR_PREC_F32_STEPS
         assert lib.lowrank_plan_bytes(ctypes.byref(m), 2, 4, ctypes.byref(opt),
                                       ctypes.byref(out2)) == 0
-        # 112 x 16 and 512 x 16 floats, each in place of an empty 256-byte slot
-        assert out2.value - out0.value == (112 * 16 * 4 - 256) + (512 * 16 * 4 - 256)
+        # 112 x 16 and 4 x 512 x 16 floats, each in place of an empty 256-byte slot
+        assert out2.value - out0.value == (112 * 16 * 4 - 256) + (2 * 512 * 16 * 4 - 256)
 
 
 def test_accel_option_checks(lib):
