@@ -3,7 +3,8 @@ times, against the oracle:
 
 * 2048 x 200000 f32 (the benchmark workload): the sampling table bit for bit,
   one whole pass X (X^T W) at p = 20, and one whole inner-solver epoch with the
-  schedule a solve of this workload uses (m = 124 steps of b = 2048 samples);
+  schedule a solve of this workload uses (m = 124 steps of b = 2048 samples),
+  with FP64 and with FP32 matrix-core steps;
 * 4096 x 500000 bf16: the sampling table bit for bit and one whole pass at
   p = 48.
 
@@ -64,15 +65,19 @@ def test_full_size_table_and_pass(torch_cuda, name):
     assert rel <= 1e-13
 
 
-def test_full_size_epoch_bench_schedule(torch_cuda):
+@pytest.mark.parametrize("precision", [0, 2])
+def test_full_size_epoch_bench_schedule(torch_cuda, precision):
     """One inner-solver epoch on 2048 x 200000 f32 with the schedule of this
     workload's solve (shift 101.647, eta 9.838e-3, m = 124, b = 2048): the
-    iterate and the residuals agree with the oracle's."""
+    iterate and the residuals agree with the oracle's.  With FP32 matrix-core
+    steps (precision 2) the bar is 1e-4 of the correction W - W_0 the steps
+    made, as for the smaller FP32-step solves."""
     import torch
     from paper_1607_02925_amd import lowrank
     name = "planted-2048x200000-f32"
     w = workloads.workload(name, device="cuda")
-    plan = lowrank.Plan(w["Xt"], w["k"], w["p"], w["eps"], seed=w["solver_seed"])
+    plan = lowrank.Plan(w["Xt"], w["k"], w["p"], w["eps"], seed=w["solver_seed"],
+                        precision=precision)
     wg, _, _ = plan.prepare()
     X = host_columns(w["Xt"], w["storage"], 0, w["n"])      # 2048 x 200000 FP64
     _, qc = oracle.build_table(wg.cpu().numpy())
@@ -83,7 +88,16 @@ def test_full_size_epoch_bench_schedule(torch_cuda):
                                      fixed_epochs=1)
     Wg = Wg.cpu().numpy()
     rel = np.linalg.norm(Wg - Wo) / np.linalg.norm(Wo)
-    print("epoch: W rel err %.2e, residuals gpu %s oracle %s" % (rel, res_g, res_o), flush=True)
-    assert rel <= 1e-11
-    np.testing.assert_allclose(res_g, res_o, rtol=1e-8)
+    print("epoch (precision %d): W rel err %.2e, residuals gpu %s oracle %s" %
+          (precision, rel, res_g, res_o), flush=True)
+    if precision == 0:
+        assert rel <= 1e-11
+        np.testing.assert_allclose(res_g, res_o, rtol=1e-8)
+    else:
+        W0 = oracle.svrg_solve(X, qc, S, lam, eta, m, b, 0.0, w["solver_seed"], 3, 60,
+                               fixed_epochs=0)[0]
+        err = np.linalg.norm(Wg - Wo) / np.linalg.norm(Wo - W0)
+        print("|W_f32 - W_oracle| / |W - W_0| = %.2e" % err, flush=True)
+        assert err <= 1e-4
+        np.testing.assert_allclose(res_g, res_o, rtol=1e-3)
     assert res_o[-1] < res_o[0]
