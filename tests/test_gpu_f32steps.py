@@ -119,3 +119,29 @@ def test_deterministic_repeat(torch_cuda):
     assert a[0] == b[0] == 0
     assert torch.equal(a[1], b[1])
     assert np.array_equal(a[2], b[2])
+
+
+def test_served_bitwise_alone(torch_cuda):
+    """FP32-step requests of mixed shapes and storage are bitwise the same alone
+    and in a mix through the server (fixed-order reductions, per-request
+    workspaces)."""
+    from paper_1607_02925_amd import lowrank
+    torch = torch_cuda
+    specs = [(256, 6000, 3, "f32"), (512, 5000, 6, "bf16"), (192, 7000, 2, "f32"),
+             (384, 4500, 5, "bf16")]
+    xs = [to_dev(torch, planted(d, n, k, 700 + d, st), st) for d, n, k, st in specs]
+    ks = [k for _, _, k, _ in specs]
+    alone = []
+    for X, k in zip(xs, ks):
+        st, U, th, _ = lowrank.Plan(X, k, k + 8, 1e-4, seed=5,
+                                    precision=lowrank.LR_PREC_F32_STEPS).solve()
+        alone.append((st, U.clone(), th))
+    srv = lowrank.Server(1 << 30, slots=4)
+    tickets = [srv.submit(X, k, k + 8, 1e-4, seed=5, precision=lowrank.LR_PREC_F32_STEPS)
+               for X, k in zip(xs, ks)]
+    outs = [srv.wait(t) for t in tickets]
+    srv.close()
+    for a, o in zip(alone, outs):
+        assert a[0] == o[0] == 0
+        assert torch.equal(a[1], o[1])
+        assert np.array_equal(a[2], o[2])
