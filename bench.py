@@ -67,8 +67,9 @@ def parse():
     ap.add_argument("--slots", type=int, default=8, help="serve: concurrent worker slots")
     ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: HBM budget (GB)")
     ap.add_argument("--rate", type=float, default=50.0, help="serve: arrivals per second")
-    ap.add_argument("--forms", default="seq,closed,open",
-                    help="serve: comma list of seq (FP32 one at a time), closed, open")
+    ap.add_argument("--forms", default="seq,closed,open,mc",
+                    help="serve: comma list of seq (FP32 one at a time), closed, open, "
+                         "mc (closed loop with matrix-core inner steps)")
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true",
@@ -176,10 +177,12 @@ def variant_leg(Xt, w, U_qk, args, name, **kw):
     return out
 
 
-def serve_run(reqs, X, slots, budget, open_loop=False):
+def serve_run(reqs, X, slots, budget, open_loop=False, matrix_core=False):
     """Push every request of `reqs` (device matrices X[i]) through a server with
     `slots` worker slots and an HBM budget; closed loop submits all at t = 0,
-    open loop at each request's arrival time.  Returns per-request results."""
+    open loop at each request's arrival time.  matrix_core: inner steps on
+    matrix cores (BF16 steps for BF16 X, FP32 steps for FP32 X) instead of FP64.
+    Returns per-request results."""
     import torch
     from paper_1607_02925_amd import lowrank
     srv = lowrank.Server(budget, slots=slots)
@@ -191,8 +194,11 @@ def serve_run(reqs, X, slots, budget, open_loop=False):
             delay = r["arrival"] - (time.time() - t0)
             if delay > 0:
                 time.sleep(delay)
+        prec = 0
+        if matrix_core:
+            prec = 1 if x.dtype == torch.bfloat16 else 2
         tickets.append(srv.submit(x, r["k"], r["p"], r["eps"], sync=False,
-                                  seed=r["solver_seed"]))
+                                  seed=r["solver_seed"], precision=prec))
     outs = [srv.wait(t) for t in tickets]
     stats = srv.stats()
     srv.close()
@@ -340,12 +346,30 @@ def serve_bench(args, dev):
     if "open" in forms:
         out["batched_open"], _ = serve_run(reqs, Xown, args.slots, budget, open_loop=True)
         log("serve batched open loop: %s" % json.dumps(out["batched_open"]))
+    if "mc" in forms:
+        out["batched_closed_matrix_core"], mc_outs = serve_run(reqs, Xown, args.slots, budget,
+                                                               matrix_core=True)
+        if closed_outs is not None:
+            # principal-angle sine of each U_k against the FP64-step batched run
+            sins = {"f32": [], "bf16": []}
+            for r, a, b in zip(reqs, closed_outs, mc_outs):
+                Ua, Ub = a[1].contiguous(), b[1].contiguous()
+                sins[r["storage"]].append(
+                    float(torch.linalg.matrix_norm(Ub - Ua @ (Ua.T @ Ub), ord=2)))
+            out["batched_closed_matrix_core"]["max_sin_vs_fp64_steps"] = {
+                k: max(v) if v else None for k, v in sins.items()}
+        log("serve batched closed loop, matrix-core steps: %s" %
+            json.dumps(out["batched_closed_matrix_core"]))
     if seq_outs is not None and closed_outs is not None:
         same = [torch.equal(a[1], b[1]) for r, a, b in zip(reqs, seq_outs, closed_outs)
                 if r["storage"] == "f32"]
         out["f32_bitwise_alone_vs_mix"] = "%d/%d" % (sum(same), len(same))
         out["speedup_batched_vs_fp32_per_request"] = \
             out["batched_closed"]["solves_per_s"] / out["fp32_per_request"]["solves_per_s"]
+        if "batched_closed_matrix_core" in out:
+            out["speedup_matrix_core_batched_vs_fp32_per_request"] = \
+                out["batched_closed_matrix_core"]["solves_per_s"] / \
+                out["fp32_per_request"]["solves_per_s"]
     return out
 
 
