@@ -6,13 +6,19 @@
 // in accumulator v (checked on the device).  As in the FP64 kernels, lane
 // (c = l % 16, q = l / 16) of a 16-row block supplies k = 4 q + s at step s.
 //
-// FP32 copies of the step difference (Dl32) and of C (C32) are kept in 1 KB
+// FP32 copies of the step difference (D32) and of C (C32) are kept in 1 KB
 // tiles: for each 16-row (or 16-sample) block and 16-column slice, lane l's
 // four values (k = 4 q .. 4 q + 3 of column c) sit at floats 4 l .. 4 l + 3,
 // so a wave reads a tile as one contiguous load.  The FP64 step difference
 // stays the master: the update computes it in FP64 from the FP32-accumulated
 // product and rounds it to the FP32 tile for the next step; the passes stay
 // FP64, so each epoch restarts from an exactly computed residual.
+//
+// One X load serves every column slice (the sample dot takes all slices in a
+// workgroup; so does the update once d has 256 row tiles).  For minibatches
+// under 256 blocks of 16 samples the sample dot splits the rows of X over two
+// workgroups that write separate partial C32 copies, which the update adds as
+// it loads them: no workgroup waits on another.
 #include "f32steps.h"
 
 #include <hip/hip_ext.h>
