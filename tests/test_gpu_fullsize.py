@@ -6,7 +6,7 @@ times, against the oracle:
   schedule a solve of this workload uses (m = 124 steps of b = 2048 samples),
   with FP64 and with FP32 matrix-core steps;
 * 4096 x 500000 bf16: the sampling table bit for bit and one whole pass at
-  p = 48.
+  p = 48, and a whole adaptive solve against the exact top-k subspace.
 
 The oracle works on column chunks of X (FP64 copies of 1-2 GB), so its memory
 stays bounded; the chunk sums of the pass reorder FP64 additions only.
@@ -101,3 +101,41 @@ def test_full_size_epoch_bench_schedule(torch_cuda, precision):
         assert err <= 1e-4
         np.testing.assert_allclose(res_g, res_o, rtol=1e-3)
     assert res_o[-1] < res_o[0]
+
+
+def test_full_size_adaptive_bf16_exact_subspace(torch_cuda):
+    """A whole solve of 4096 x 500000 bf16 (k = 32, p = 48, eps = 1e-4) by the
+    adaptive partitioning of Algorithm "main", against the definition of the
+    answer: the top-k eigenvectors of X X^T for the stored X, from an FP64 Gram
+    summed over column chunks on the CPU and LAPACK's eigh.  (The q = k branch
+    needs about 300 outer iterations on this spectrum; its trajectory is
+    checked on the oracle-sized 512 x 16384 version.)"""
+    import time
+    import torch
+    from paper_1607_02925_amd import lowrank
+    w = workloads.workload("planted-4096x500000-bf16", device="cuda")
+    k, p = w["k"], w["p"]
+    plan = lowrank.Plan(w["Xt"], k, p, w["eps"], seed=w["solver_seed"], adaptive=1)
+    t = time.time()
+    st, U, theta, rep = plan.solve()
+    torch.cuda.synchronize()
+    print("adaptive solve: status %d in %.2f s, %d passes, %d inner steps, intervals %s" %
+          (st, time.time() - t, rep["passes"], rep["steps"],
+           [(iv["s"], iv["q"], iv["branch"], iv["iters"]) for iv in rep["intervals"]]),
+          flush=True)
+    assert st == 0
+    d, n = w["d"], w["n"]
+    gram = np.zeros((d, d))
+    for c0 in range(0, n, CHUNK):
+        xc = host_columns(w["Xt"], w["storage"], c0, min(n, c0 + CHUNK))
+        gram += xc @ xc.T
+        del xc
+    ev, V = np.linalg.eigh(gram)
+    ev, V = ev[::-1], V[:, ::-1]
+    Ug = U.cpu().numpy()
+    sin = oracle.sin_theta(V[:, :k], Ug)
+    rel = np.max(np.abs(theta - ev[:k]) / ev[:k])
+    print("sin vs exact top-%d subspace %.2e, Ritz values rel err %.2e, sin vs planted %.2e" %
+          (k, sin, rel, oracle.sin_theta(w["U"][:, :k], Ug)), flush=True)
+    assert sin <= 1e-6
+    assert rel <= 1e-10
