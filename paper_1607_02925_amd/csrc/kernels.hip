@@ -1248,11 +1248,14 @@ __global__ __launch_bounds__(NT) void k_chol_rinv(const double* __restrict__ G, 
 __global__ __launch_bounds__(NT) void k_jacobi(const double* __restrict__ H, int m,
                                                double* __restrict__ vals,
                                                double* __restrict__ vecs) {
-  __shared__ double a[SM][SM];
-  __shared__ double v[SM][SM];
+  // one double of padding per row: column walks (a[row][P] over rows) then hit
+  // every LDS bank instead of one
+  __shared__ double a[SM][SM + 1];
+  __shared__ double v[SM][SM + 1];
   __shared__ double rc[SM / 2], rs[SM / 2];
   __shared__ int rp[SM / 2], rq[SM / 2];
-  __shared__ double red[NT];
+  constexpr int NWJ = NT / 64;
+  __shared__ double roff[NWJ], rtot[NWJ];
   __shared__ int stop;
   const int t = threadIdx.x;
   for (int e = t; e < m * m; e += NT) {
@@ -1265,6 +1268,8 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double* __restrict__ H, int
   const int np = m2 / 2;
   const int nr = m2 - 1;
   for (int sweep = 0; sweep < 60; ++sweep) {
+    // stopping test: off-diagonal and total squared mass, summed within each wave
+    // by shuffles and then over the NWJ waves in a fixed order
     double off = 0.0, tot = 0.0;
     for (int e = t; e < m * m; e += NT) {
       const int i = e % m, j = e / m;
@@ -1272,21 +1277,25 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double* __restrict__ H, int
       tot += x;
       if (i != j) off += x;
     }
-    red[t] = off;
-    __syncthreads();
-    for (int k = NT / 2; k > 0; k >>= 1) {
-      if (t < k) red[t] += red[t + k];
-      __syncthreads();
+#pragma unroll
+    for (int k = 32; k > 0; k >>= 1) {
+      off += __shfl_down(off, k, 64);
+      tot += __shfl_down(tot, k, 64);
     }
-    const double offs = red[0];
-    __syncthreads();
-    red[t] = tot;
-    __syncthreads();
-    for (int k = NT / 2; k > 0; k >>= 1) {
-      if (t < k) red[t] += red[t + k];
-      __syncthreads();
+    if (t % 64 == 0) {
+      roff[t / 64] = off;
+      rtot[t / 64] = tot;
     }
-    if (t == 0) stop = (offs <= 1e-32 * red[0]) || m < 2;
+    __syncthreads();
+    if (t == 0) {
+      double so = roff[0], st = rtot[0];
+#pragma unroll
+      for (int w = 1; w < NWJ; ++w) {
+        so += roff[w];
+        st += rtot[w];
+      }
+      stop = (so <= 1e-32 * st) || m < 2;
+    }
     __syncthreads();
     if (stop) break;
     for (int r = 0; r < nr; ++r) {
@@ -1335,17 +1344,14 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double* __restrict__ H, int
         if (P >= 0) {
           const double c = rc[pi], s = rs[pi];
           const double aP = a[row][P], aQ = a[row][Q];
-          a[row][P] = c * aP - s * aQ;
-          a[row][Q] = s * aP + c * aQ;
+          // the entry the rotation annihilates is stored as an exact zero
+          const bool zP = row == Q && s != 0.0, zQ = row == P && s != 0.0;
+          a[row][P] = zP ? 0.0 : c * aP - s * aQ;
+          a[row][Q] = zQ ? 0.0 : s * aP + c * aQ;
           const double vP = v[row][P], vQ = v[row][Q];
           v[row][P] = c * vP - s * vQ;
           v[row][Q] = s * vP + c * vQ;
         }
-      }
-      __syncthreads();
-      if (t < np && rp[t] >= 0 && rs[t] != 0.0) {
-        a[rp[t]][rq[t]] = 0.0;
-        a[rq[t]][rp[t]] = 0.0;
       }
       __syncthreads();
     }
