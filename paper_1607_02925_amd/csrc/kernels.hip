@@ -844,14 +844,30 @@ __global__ __launch_bounds__(NT) void k_reduce_y(const double* __restrict__ part
                                                  const double* __restrict__ A, double beta,
                                                  const double* __restrict__ B, double gamma,
                                                  double* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (e >= cnt) return;
+  // RG threads per element, each summing a consecutive quarter of the splits in
+  // split order; the quarters are then added in order (a fixed order)
+  constexpr int RG = 4, EPB = NT / RG;
+  __shared__ double qs[RG][EPB];
+  const int t = threadIdx.x, el = t % EPB, g = t / EPB;
+  const int64_t e = (int64_t)blockIdx.x * EPB + el;
+  const int per = (nsplit + RG - 1) / RG;
+  const int k0 = min(nsplit, g * per), k1 = min(nsplit, k0 + per);
   double s = 0.0;
-  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * cnt + e];
-  double v = alpha * s;
-  if (A) v += beta * A[e];
-  if (B) v += gamma * B[e];
-  out[e] = v;
+  if (e < cnt) {
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) s += part[(int64_t)k * cnt + e];
+  }
+  qs[g][el] = s;
+  __syncthreads();
+  if (g == 0 && e < cnt) {
+    double v = qs[0][el];
+#pragma unroll
+    for (int h = 1; h < RG; ++h) v += qs[h][el];
+    v = alpha * v;
+    if (A) v += beta * A[e];
+    if (B) v += gamma * B[e];
+    out[e] = v;
+  }
 }
 
 // Inner-step update for a tile of 16 rows and the 16-column slice nt = blockIdx.y:
@@ -1142,27 +1158,39 @@ __global__ __launch_bounds__(NT) void k_sum_final(const double* __restrict__ par
   if (t == 0) out[0] = ss[0];
 }
 
-// D = A M + beta C ; one thread per row, M in LDS.
+// D = A M + beta C for a d x p block A (column-major, leading dimension d) and a
+// p x q block M: one thread per row.  M sits in LDS with zero rows past p (and
+// zero columns past q), so the row's entries of A can be fetched UNR at a time
+// from clamped, in-bounds addresses and their latencies overlap; the extra
+// products are exact zeros and the sums keep their order.
 template <int PM>
 __global__ __launch_bounds__(NT) void k_gemm_small(int64_t d, int p, int q,
                                                    const double* __restrict__ A,
                                                    const double* __restrict__ M, int ldm,
                                                    double* __restrict__ D, double beta,
                                                    const double* __restrict__ C) {
-  __shared__ double ms[64 * 64];
+  constexpr int UNR = PM >= 48 ? 4 : 8;   // wide blocks: fewer loads ahead, no spills
+  constexpr int LDM = 64 + UNR;           // LDS rows per column of M: p <= 64, rounded up to UNR
+  __shared__ double ms[PM * LDM];
   const int t = threadIdx.x;
-  for (int e = t; e < p * q; e += NT) ms[e] = M[(e % p) + (int64_t)(e / p) * ldm];
+  for (int e = t; e < PM * LDM; e += NT) {
+    const int i = e % LDM, j = e / LDM;
+    ms[e] = (i < p && j < q) ? M[i + (int64_t)j * ldm] : 0.0;
+  }
   __syncthreads();
   const int64_t row = (int64_t)blockIdx.x * NT + t;
   if (row >= d) return;
   double acc[PM];
 #pragma unroll
   for (int j = 0; j < PM; ++j) acc[j] = 0.0;
-  for (int i = 0; i < p; ++i) {
-    const double a = A[(int64_t)i * d + row];
+  for (int i0 = 0; i0 < p; i0 += UNR) {
+    double a[UNR];
 #pragma unroll
-    for (int j = 0; j < PM; ++j)
-      if (j < q) acc[j] = fma(a, ms[i + j * p], acc[j]);
+    for (int u = 0; u < UNR; ++u) a[u] = A[(int64_t)min(i0 + u, p - 1) * d + row];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int j = 0; j < PM; ++j) acc[j] = fma(a[u], ms[(i0 + u) + j * LDM], acc[j]);
   }
 #pragma unroll
   for (int j = 0; j < PM; ++j)
@@ -1635,7 +1663,8 @@ hipError_t pass_xt(const XView& X, const double* T, int PC, int p, const PassBuf
 #undef LR_PASS2
   if (!done) return hipErrorInvalidValue;
   const int64_t cnt = X.d * p;
-  k_reduce_y<<<nblocks(cnt), NT, 0, st>>>(pb.Ypart, pb.nsplit, cnt, alpha, A, beta, B, gamma, out);
+  k_reduce_y<<<nblocks(cnt, NT / 4), NT, 0, st>>>(pb.Ypart, pb.nsplit, cnt, alpha, A, beta, B,
+                                                  gamma, out);
   return hipGetLastError();
 }
 
