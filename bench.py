@@ -358,19 +358,38 @@ def serve_bench(args, dev):
                     float(torch.linalg.matrix_norm(Ub - Ua @ (Ua.T @ Ub), ord=2)))
             out["batched_closed_matrix_core"]["max_sin_vs_fp64_steps"] = {
                 k: max(v) if v else None for k, v in sins.items()}
+            out["matrix_core_agrees"] = all(v is None or v <= 1e-10 for v in
+                                            out["batched_closed_matrix_core"]
+                                            ["max_sin_vs_fp64_steps"].values())
         log("serve batched closed loop, matrix-core steps: %s" %
             json.dumps(out["batched_closed_matrix_core"]))
     if seq_outs is not None and closed_outs is not None:
         same = [torch.equal(a[1], b[1]) for r, a, b in zip(reqs, seq_outs, closed_outs)
                 if r["storage"] == "f32"]
         out["f32_bitwise_alone_vs_mix"] = "%d/%d" % (sum(same), len(same))
+        out["alone_equals_mix"] = all(same)
         out["speedup_batched_vs_fp32_per_request"] = \
             out["batched_closed"]["solves_per_s"] / out["fp32_per_request"]["solves_per_s"]
         if "batched_closed_matrix_core" in out:
             out["speedup_matrix_core_batched_vs_fp32_per_request"] = \
                 out["batched_closed_matrix_core"]["solves_per_s"] / \
                 out["fp32_per_request"]["solves_per_s"]
+    failed = [name for name in ("fp32_per_request", "batched_closed", "batched_open",
+                                "batched_closed_matrix_core")
+              if name in out and out[name]["failed"]]
+    out["consistent"] = (not failed and out.get("alone_equals_mix", True) and
+                         out.get("matrix_core_agrees", True))
     return out
+
+
+def serve_consistency_exit(serve):
+    """Non-zero exit when the serving legs disagree with themselves: a request
+    that failed, an FP32 request whose U_k is not bitwise the same alone and in
+    the mix, or a matrix-core result off the FP64-step one."""
+    if serve is not None and not serve.get("consistent", True):
+        log("serving results are inconsistent (failed requests, alone != mix, or "
+            "matrix-core != FP64 steps); see the serve object")
+        sys.exit(3)
 
 
 def main():
@@ -389,6 +408,7 @@ def main():
     if args.mode == "serve":
         out = serve_bench(args, dev)
         print(json.dumps({"mode": "serve", **out}), flush=True)
+        serve_consistency_exit(out)
         return
     if args.mode == "sparse":
         out = sparse_bench(args, dev)
@@ -545,6 +565,7 @@ def main():
         torch.cuda.empty_cache()
         out["serve"] = serve_bench(args, dev)
     print(json.dumps(out), flush=True)
+    serve_consistency_exit(out.get("serve"))
 
 
 if __name__ == "__main__":

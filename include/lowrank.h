@@ -59,7 +59,8 @@ typedef enum {
                        positive: lambda not above lambda_1; or shift tuning did not
                        reach the interval of eq. (shiftClose) within max_shift_rounds */
   LR_ENOTSPD = 6,   /* Cholesky-QR met a Gram matrix that is not positive definite
-                       (block lost rank) */
+                       (block lost rank: a Cholesky pivot at or below 1e-14 of
+                       its diagonal entry, e.g. when rank(X) < p) */
   LR_EDEVICE = 7,   /* a HIP runtime call or kernel launch failed */
   LR_EBUSY = 8
 } lr_status;
@@ -162,7 +163,16 @@ typedef struct lr_schedule {
  *                   are reported in lr_report.  An outer step counts as
  *                   an epoch; a solve may take max_epochs ceil(1 / sqrt(q))
  *                   of them, q = mu / (mu + kappa).  0 (default): plain SVRG
- *                   epochs.  Not with a replay schedule. */
+ *                   epochs.  Not with a replay schedule.
+ *   fill_workspace  1: when the plan is made, fill its whole device workspace
+ *                   with the byte 0xFF (a NaN in every floating-point type the
+ *                   library uses) by a kernel, so that any read of workspace
+ *                   memory the solve has not written first changes the result.
+ *                   For testing; 0 (default) leaves the workspace as found.
+ *   shift_start     > 0: Algorithm "shiftTune" starts from lambda = shift_start
+ *                   (with the strong-convexity estimate max(lambda - theta_1 -
+ *                   ||r_1||, Delta/30)) instead of the start shift_mode names;
+ *                   0 (default): shift_mode decides. */
 typedef enum { LR_PREC_F64 = 0, LR_PREC_BF16_STEPS = 1, LR_PREC_F32_STEPS = 2 } lr_precision;
 
 typedef struct lr_options {
@@ -177,6 +187,8 @@ typedef struct lr_options {
   int32_t adaptive;
   int32_t norm;
   int32_t accel;
+  int32_t fill_workspace;
+  double shift_start;
 } lr_options;
 
 /* What a solve did.  Host struct filled by lowrank_solve. */

@@ -20,6 +20,12 @@ class NotSPD(Exception):
     pass
 
 
+# A Cholesky pivot below this fraction of its diagonal entry marks the block
+# as numerically rank deficient (its Gram matrix is then treated as not
+# positive definite).
+PIVOT_REL = 1e-14
+
+
 def cholqr(w):
     g = w.T @ w
     g = 0.5 * (g + g.T)
@@ -27,6 +33,9 @@ def cholqr(w):
         lower = np.linalg.cholesky(g)
     except np.linalg.LinAlgError as e:
         raise NotSPD(str(e))
+    piv = np.diag(lower) ** 2
+    if not np.all(piv > PIVOT_REL * np.diag(g)):
+        raise NotSPD("pivot below %g of its diagonal" % PIVOT_REL)
     # S = W R^{-1} with R = L^T, i.e. S^T = L^{-1} W^T
     s = sla.solve_triangular(lower, w.T, lower=True).T
     return s, lower.T

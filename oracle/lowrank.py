@@ -55,6 +55,7 @@ class LowRankError(Exception):
 class Options:
     seed: int = 0
     shift_mode: str = "fast"        # "fast": theta_1 + ||r_1|| + Delta/10 ; "literal": 1.5 theta_1
+    shift_start: float = 0.0        # > 0: shift tuning starts from this lambda instead
     est_iters: int = 4
     max_outer: int = 2000
     max_epochs: int = 60
@@ -238,7 +239,10 @@ def tune_shift(X, qc, S_est, theta, res, delta, fro2, seed, opt, n, Ud=None, sol
     rounds, history).  Ud: deflation basis; solve0: solve index of the first
     round; out (dict): receives "nu", the Ritz values of the last round."""
     t1, r1 = theta[0], res[0]
-    if opt.shift_mode == "literal":
+    if opt.shift_start > 0:
+        lam = opt.shift_start
+        mu = max(lam - t1 - r1, delta / 30.0)
+    elif opt.shift_mode == "literal":
         lam = 1.5 * t1
         mu = max(lam - t1 - r1, delta / 30.0)
     else:
@@ -347,7 +351,17 @@ def validate(d, n, k, p):
 def solve(xt, storage, k, p, eps, opt=None, replay=None):
     """Full oracle run.  ``replay``: a Schedule whose lam, mu_hat, eta, m, b,
     first_solve, outer and epochs are used instead of the estimate, shift and
-    stopping decisions."""
+    stopping decisions.  A block that loses rank (Cholesky-QR meets a Gram
+    matrix that is not positive definite, e.g. rank(X) < p, against the full
+    column rank the QR step of Algorithm "subspace iteration" needs) is
+    reported as LR_ENOTSPD."""
+    try:
+        return _solve(xt, storage, k, p, eps, opt, replay)
+    except NotSPD as e:
+        raise LowRankError(LR_ENOTSPD, "Cholesky-QR: Gram matrix not positive definite (%s)" % e)
+
+
+def _solve(xt, storage, k, p, eps, opt=None, replay=None):
     opt = opt or Options()
     X = decode(xt, storage)
     d, n = X.shape

@@ -193,6 +193,8 @@ struct lr_plan_s {
   }
 
   lr_status sparse_setup();
+  lr_status device_structure(int* bad);
+  lr_status confirm_structure(int device_flag);
 
   lr_status gram_dd(const double* A, int pa, const double* B, int pb_, double* out) {
     LR_HIP(lr::gram(A, 1, d, pa, B, 1, d, pb_, d, part, out, st));
@@ -483,7 +485,10 @@ lr_status lr_plan_s::tune_shift(const double* theta, const double* resn, double 
                                 int* rounds_out, double* nu_out) {
   const double t1 = theta[0], r1 = resn[0];
   double lam, mu;
-  if (opt.shift_mode == 1) {
+  if (opt.shift_start > 0) {
+    lam = opt.shift_start;
+    mu = std::max(lam - t1 - r1, delta / 30.0);
+  } else if (opt.shift_mode == 1) {
     lam = 1.5 * t1;
     mu = std::max(lam - t1 - r1, delta / 30.0);
   } else {
@@ -888,6 +893,80 @@ size_t lr_plan_s::carve(char* base) {
   return (off + 255) & ~(size_t)255;
 }
 
+// Device structure checks of the caller's CSC arrays: *bad = 0 when sound, 1
+// when col_ptr does not rise from 0 to nnz, 2 when a row id is out of [0, d) or
+// not increasing within its column.
+lr_status lr_plan_s::device_structure(int* bad) {
+  *bad = 0;
+  LR_HIP(hipMemsetAsync(dbad, 0, sizeof(int), st));
+  LR_HIP(lr::csc_check_ptr(Xs, dbad, st));
+  LR_CHECK(read(bad, dbad, sizeof(int)));
+  if (*bad) return LR_OK;
+  LR_HIP(lr::csc_check_rows(Xs, dbad, st));
+  LR_CHECK(read(bad, dbad, sizeof(int)));
+  return LR_OK;
+}
+
+namespace {
+// The same structure rules on host copies; "" when sound, else the first
+// violation.
+std::string host_structure(const std::vector<int32_t>& cp, const std::vector<int32_t>& ri,
+                           int64_t n, int64_t nnz, int64_t d) {
+  char buf[160];
+  if (cp[0] != 0 || cp[n] != nnz) {
+    std::snprintf(buf, sizeof buf, "CSC col_ptr must rise from 0 to nnz (col_ptr[0] = %d, "
+                  "col_ptr[n] = %d, nnz = %lld)", cp[0], cp[n], (long long)nnz);
+    return buf;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (cp[i + 1] < cp[i] || cp[i] < 0 || cp[i] > nnz) {
+      std::snprintf(buf, sizeof buf, "CSC col_ptr must rise from 0 to nnz (col_ptr[%lld] = %d, "
+                    "col_ptr[%lld] = %d)", (long long)i, cp[i], (long long)(i + 1), cp[i + 1]);
+      return buf;
+    }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = cp[i]; k < cp[i + 1]; ++k)
+      if (ri[k] < 0 || ri[k] >= d || (k > cp[i] && ri[k] <= ri[k - 1])) {
+        std::snprintf(buf, sizeof buf, "CSC row ids must lie in [0, d) and increase within each "
+                      "column (column %lld, entry %lld: row %d)", (long long)i, (long long)k,
+                      ri[k]);
+        return buf;
+      }
+  return "";
+}
+}  // namespace
+
+// A device check rejected X: copy col_ptr and row_idx to the host and apply the
+// same rules there.  If the host copy breaks them, LR_EINVAL names the first
+// violation.  If it does not, the device check read something other than what
+// the arrays hold; it is run once more, and a second rejection is LR_EDEVICE
+// (the input is not blamed for what the device saw).
+lr_status lr_plan_s::confirm_structure(int device_flag) {
+  const int64_t n = Xs.n, nnz = Xs.nnz;
+  std::vector<int32_t> cp(n + 1), ri(std::max<int64_t>(nnz, 1));
+  LR_HIP(hipStreamSynchronize(st));
+  LR_HIP(hipMemcpy(cp.data(), Xs.cp, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  const bool ptr_ok = cp[0] == 0 && cp[n] == nnz &&
+                      [&] {
+                        for (int64_t i = 0; i < n; ++i)
+                          if (cp[i + 1] < cp[i] || cp[i] < 0) return false;
+                        return true;
+                      }();
+  if (ptr_ok && nnz > 0)
+    LR_HIP(hipMemcpy(ri.data(), Xs.ri, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+  const std::string why = host_structure(cp, ri, n, nnz, d);
+  if (!why.empty()) return fail(LR_EINVAL, why);
+  int again = 0;
+  LR_CHECK(device_structure(&again));
+  if (again) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "device check of the CSC structure flagged %d then %d, but a "
+                  "host copy of col_ptr and row_idx is sound", device_flag, again);
+    return fail(LR_EDEVICE, buf);
+  }
+  return LR_OK;
+}
+
 lr_status lr_plan_s::sparse_setup() {
   const int64_t nnz = Xs.nnz;
   const size_t elt = Xs.dt == LR_F64 ? 8 : Xs.dt == LR_F32 ? 4 : 2;
@@ -898,17 +977,17 @@ lr_status lr_plan_s::sparse_setup() {
       return fail(LR_ENOMEM, "device allocation failed");
     }
     sp_allocs.push_back(*ptr);
+    if (opt.fill_workspace && lr::fill_bytes(*ptr, std::max<size_t>(bytes, 1) & ~(size_t)3, 0xFF,
+                                             st) != hipSuccess)
+      return fail(LR_EDEVICE, "workspace fill failed");
     return LR_OK;
   };
-  // structure checks; row ids are read only once col_ptr is known to be sound
+  // structure checks on the device; row ids are read only once col_ptr is
+  // known to be sound.  A rejection is confirmed on a host copy of the arrays
+  // before it is reported (see confirm_structure).
   int bad = 0;
-  LR_HIP(hipMemsetAsync(dbad, 0, sizeof(int), st));
-  LR_HIP(lr::csc_check_ptr(Xs, dbad, st));
-  LR_CHECK(read(&bad, dbad, sizeof(int)));
-  if (bad) return fail(LR_EINVAL, "CSC col_ptr must rise from 0 to nnz");
-  LR_HIP(lr::csc_check_rows(Xs, dbad, st));
-  LR_CHECK(read(&bad, dbad, sizeof(int)));
-  if (bad) return fail(LR_EINVAL, "CSC row ids must lie in [0, d) and increase within each column");
+  LR_CHECK(device_structure(&bad));
+  if (bad) LR_CHECK(confirm_structure(bad));
   // row-ordered copy: stable radix sort of the row ids keeps columns ascending
   void *col = nullptr, *val = nullptr;
   LR_CHECK(keep(&col, (size_t)nnz * 4));
@@ -1016,6 +1095,10 @@ lr_status plan_check(const lr_matrix* Xm, int k, int p, double eps, const lr_opt
     if (opt->adaptive < 0 || opt->adaptive > 1) return fail(LR_EINVAL, "adaptive must be 0 or 1");
     if (opt->norm < 0 || opt->norm > 1) return fail(LR_EINVAL, "norm must be 0 or 1");
     if (opt->accel < 0 || opt->accel > 1) return fail(LR_EINVAL, "accel must be 0 or 1");
+    if (opt->fill_workspace < 0 || opt->fill_workspace > 1)
+      return fail(LR_EINVAL, "fill_workspace must be 0 or 1");
+    if (!(opt->shift_start >= 0) || !std::isfinite(opt->shift_start))
+      return fail(LR_EINVAL, "shift_start must be a finite value >= 0");
     if (opt->accel && opt->replay)
       return fail(LR_EINVAL, "a replay schedule drives the plain inner solver only");
     if (opt->adaptive &&
@@ -1113,6 +1196,9 @@ lr_status plan_make(lr_plan_s** out, const lr_matrix* Xm, int k, int p, double e
     s = fail(LR_ENOMEM, "device allocation failed");
   }
   if (s == LR_OK) pl->carve((char*)pl->ws);
+  if (s == LR_OK && pl->opt.fill_workspace &&
+      lr::fill_bytes(pl->ws, need, 0xFF, st) != hipSuccess)
+    s = fail(LR_EDEVICE, "workspace fill failed");
   if (s == LR_OK && host) {
     pl->owns_host = false;
     pl->hpin = host->hpin;
@@ -1186,6 +1272,8 @@ void lowrank_options_default(lr_options* o) {
   o->adaptive = 0;
   o->norm = 0;
   o->accel = 0;
+  o->fill_workspace = 0;
+  o->shift_start = 0.0;
 }
 
 lr_status lowrank_plan(lr_plan* out, const lr_matrix* Xm, int k, int p, double eps,

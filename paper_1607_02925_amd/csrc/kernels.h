@@ -116,5 +116,7 @@ hipError_t residual_norms(const double* A, const double* B, const double* theta,
                           double* out, hipStream_t st);
 // Make each column's largest-magnitude entry positive (first index on ties).
 hipError_t sign_fix(double* U, int64_t d, int k, hipStream_t st);
+// Every byte of [p, p + bytes) set to `byte` by a kernel (p 4-byte aligned).
+hipError_t fill_bytes(void* p, size_t bytes, unsigned char byte, hipStream_t st);
 
 }  // namespace lr

@@ -1216,24 +1216,29 @@ __global__ __launch_bounds__(NT) void k_lincomb(int64_t count, double a,
 // ---------------------------------------------------------------------------
 // Small dense kernels, one workgroup, m <= 64.
 constexpr int SM = 64;
+constexpr double CHOL_PIVOT_REL = 1e-14;
 
 __global__ __launch_bounds__(NT) void k_chol_rinv(const double* __restrict__ G, int m,
                                                   double* __restrict__ Rinv,
                                                   int* __restrict__ info) {
   __shared__ double a[SM][SM];
   __shared__ double li[SM][SM];
+  __shared__ double g0[SM];
   __shared__ int bad;
   const int t = threadIdx.x;
   if (t == 0) bad = 0;
   for (int e = t; e < m * m; e += NT) {
     const int i = e % m, j = e / m;
     a[i][j] = 0.5 * (G[i + j * m] + G[j + i * m]);
+    if (i == j) g0[i] = a[i][j];
   }
   __syncthreads();
+  // a pivot at or below CHOL_PIVOT_REL of its diagonal entry: the block has
+  // (numerically) lost rank, reported like a negative pivot
   for (int j = 0; j < m; ++j) {
     if (t == 0) {
       const double dj = a[j][j];
-      if (!(dj > 0.0) || !isfinite(dj)) {
+      if (!(dj > CHOL_PIVOT_REL * g0[j]) || !isfinite(dj)) {
         bad = 1;
         a[j][j] = 1.0;
       } else {
@@ -1440,21 +1445,27 @@ __global__ __launch_bounds__(NT) void k_residual_norms(const double* __restrict_
   if (t == 0) out[i] = sqrt(ss[0]);
 }
 
+// The signed value of the winning entry travels with its magnitude and index
+// through the reduction: the column is rewritten in place, so no thread may
+// look the entry up in memory again (its owner may already have flipped it).
 __global__ __launch_bounds__(NT) void k_sign_fix(double* __restrict__ U, int64_t d) {
-  __shared__ double bv[NT];
+  __shared__ double bv[NT], bs[NT];
   __shared__ int64_t bi[NT];
   const int t = threadIdx.x;
   double* col = U + (int64_t)blockIdx.x * d;
-  double best = -1.0;
+  double best = -1.0, sv = 0.0;
   int64_t am = 0;
   for (int64_t r = t; r < d; r += NT) {
-    const double x = fabs(col[r]);
+    const double v = col[r];
+    const double x = fabs(v);
     if (x > best) {
       best = x;
+      sv = v;
       am = r;
     }
   }
   bv[t] = best;
+  bs[t] = sv;
   bi[t] = am;
   __syncthreads();
   for (int k = NT / 2; k > 0; k >>= 1) {
@@ -1463,13 +1474,25 @@ __global__ __launch_bounds__(NT) void k_sign_fix(double* __restrict__ U, int64_t
       const int64_t oi = bi[t + k];
       if (o > bv[t] || (o == bv[t] && oi < bi[t])) {
         bv[t] = o;
+        bs[t] = bs[t + k];
         bi[t] = oi;
       }
     }
     __syncthreads();
   }
-  const double sg = col[bi[0]] < 0.0 ? -1.0 : 1.0;
+  const double sg = bs[0] < 0.0 ? -1.0 : 1.0;
   for (int64_t r = t; r < d; r += NT) col[r] *= sg;
+}
+
+__global__ __launch_bounds__(NT) void k_fill_u32(uint32_t* __restrict__ p, int64_t words,
+                                                  uint32_t v) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < words;
+       e += (int64_t)gridDim.x * NT)
+    p[e] = v;
+}
+
+__global__ void k_fill_tail(unsigned char* __restrict__ p, int64_t bytes, unsigned char v) {
+  if (threadIdx.x < bytes) p[threadIdx.x] = v;
 }
 
 inline unsigned nblocks(int64_t count, int per = NT) {
@@ -1804,6 +1827,18 @@ hipError_t shift_inverse(const double* vals, const double* Q, int m, double lam,
 hipError_t residual_norms(const double* A, const double* B, const double* theta, int64_t d, int m,
                           double* out, hipStream_t st) {
   k_residual_norms<<<m, NT, 0, st>>>(A, B, theta, d, out);
+  return hipGetLastError();
+}
+
+hipError_t fill_bytes(void* p, size_t bytes, unsigned char byte, hipStream_t st) {
+  if ((uintptr_t)p % 4) return hipErrorInvalidValue;
+  const int64_t words = (int64_t)(bytes / 4);
+  const uint32_t v = byte * 0x01010101u;
+  if (words > 0)
+    k_fill_u32<<<(unsigned)std::min<int64_t>(nblocks(words), 4096), NT, 0, st>>>(
+        (uint32_t*)p, words, v);
+  if (bytes % 4)
+    k_fill_tail<<<1, 4, 0, st>>>((unsigned char*)p + words * 4, (int64_t)(bytes % 4), byte);
   return hipGetLastError();
 }
 

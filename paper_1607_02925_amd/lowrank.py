@@ -45,7 +45,8 @@ class lr_options(ctypes.Structure):
                 ("eta_scale", ctypes.c_double), ("tau_shift", ctypes.c_double),
                 ("replay", ctypes.POINTER(lr_schedule)), ("timing", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("adaptive", ctypes.c_int32),
-                ("norm", ctypes.c_int32), ("accel", ctypes.c_int32)]
+                ("norm", ctypes.c_int32), ("accel", ctypes.c_int32),
+                ("fill_workspace", ctypes.c_int32), ("shift_start", ctypes.c_double)]
 
 
 class lr_report(ctypes.Structure):
@@ -250,7 +251,8 @@ def _matrix(Xt):
 
 def make_options(seed=0, shift_mode=0, est_iters=4, max_outer=2000, max_epochs=60,
                  max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0, tau_shift=1e-2,
-                 replay=None, timing=0, precision=0, adaptive=0, norm=0, accel=0):
+                 replay=None, timing=0, precision=0, adaptive=0, norm=0, accel=0,
+                 fill_workspace=0, shift_start=0.0):
     """lr_options plus the host objects it points to (kept alive by the caller)."""
     lib = load_library()
     opt = lr_options()
@@ -263,6 +265,8 @@ def make_options(seed=0, shift_mode=0, est_iters=4, max_outer=2000, max_epochs=6
     opt.adaptive = adaptive
     opt.norm = norm
     opt.accel = accel
+    opt.fill_workspace = fill_workspace
+    opt.shift_start = float(shift_start)
     keep = None
     if replay is not None:
         sc, arr = replay.to_c()
@@ -289,7 +293,7 @@ class Plan:
     def __init__(self, Xt, k, p, eps, seed=0, shift_mode=0, est_iters=4, max_outer=2000,
                  max_epochs=60, max_shift_rounds=30, polish=0, batch=0, eta_scale=1.0,
                  tau_shift=1e-2, replay=None, timing=0, precision=0, adaptive=0, norm=0,
-                 accel=0):
+                 accel=0, fill_workspace=0, shift_start=0.0):
         import torch
         self.lib = load_library()
         self._mat = _matrix(Xt)
@@ -301,7 +305,8 @@ class Plan:
             seed=seed, shift_mode=shift_mode, est_iters=est_iters, max_outer=max_outer,
             max_epochs=max_epochs, max_shift_rounds=max_shift_rounds, polish=polish, batch=batch,
             eta_scale=eta_scale, tau_shift=tau_shift, replay=replay, timing=timing,
-            precision=precision, adaptive=adaptive, norm=norm, accel=accel)
+            precision=precision, adaptive=adaptive, norm=norm, accel=accel,
+            fill_workspace=fill_workspace, shift_start=shift_start)
         self._opt = opt
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -70,3 +70,41 @@ def test_plan_rejects_bad_sizes_without_gpu(lib):
     assert lib.lowrank_plan(ctypes.byref(h), ctypes.byref(m), 2, 4, 1e-4, None, None) == \
         lowrank.LR_EINVAL
     assert b"null" in lib.lowrank_last_error()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the header's sizes and field
+    offsets (a mismatch would let the library write past a caller's struct)."""
+    import ctypes
+    import shutil
+    from paper_1607_02925_amd import lowrank
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"lr_matrix": lowrank.lr_matrix, "lr_schedule": lowrank.lr_schedule,
+               "lr_options": lowrank.lr_options, "lr_report": lowrank.lr_report,
+               "lr_ticket_info": lowrank.lr_ticket_info,
+               "lr_server_stats": lowrank.lr_server_stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lowrank.h"',
+             "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for f, _ in cls._fields_:
+            cf = "lambda" if f == "lam" else f
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, f, name, cf))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = str(tmp_path / "layout")
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", exe],
+                   check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    seen = {}
+    for line in out:
+        if line.strip():
+            a, b, c = line.split()
+            seen[(a, b)] = int(c)
+    for name, cls in structs.items():
+        assert seen[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert seen[(name, f)] == getattr(cls, f).offset, (name, f)

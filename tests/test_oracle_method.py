@@ -24,7 +24,8 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.lowrank import (LowRankError, LR_ESHIFT, LR_EINVAL, LR_ENOGAP, Options, Schedule,
+from oracle.lowrank import (LowRankError, LR_ESHIFT, LR_EINVAL, LR_ENOGAP, LR_ENOTSPD, Options,
+                            Schedule,
                             svrg_step, svrg_solve, si_iterate, estimate_phase, tune_shift, solve,
                             decode)
 from oracle.sampling import column_sq_norms, build_table
@@ -203,3 +204,38 @@ def test_error_paths():
     with pytest.raises(LowRankError) as ei:
         solve(np.ascontiguousarray(X.T), "f64", 2, 4, 1e-3, Options(seed=1))
     assert ei.value.code == LR_ENOGAP
+
+
+def test_shift_tuning_from_below_the_interval():
+    """A start inside (lambda_1, lambda_1 + Delta/27): the first estimate of
+    lambda - lambda_1 lies below the interval of eq. (shiftClose), so lambda is
+    raised by Delta/10 once and then lands in the interval (exact eigenvalue
+    from the planted spectrum)."""
+    w = workloads.workload("planted-256x2048-f64")
+    X = decode(w["Xt"], "f64")
+    k, p = w["k"], w["p"]
+    S_est, theta, res = estimate_phase(X, k, p, w["solver_seed"], 4)
+    wn = column_sq_norms(X)
+    _, qc = build_table(wn)
+    delta = (theta[k - 1] - theta[p - 1]) / 1.5
+    lam1 = w["sigma"][0] ** 2
+    opt = Options(seed=w["solver_seed"], shift_start=lam1 + delta / 50)
+    lam, mu, rounds, hist = tune_shift(X, qc, S_est, theta, res, delta, float(wn.sum()),
+                                       opt.seed, opt, X.shape[1])
+    assert rounds == 2
+    assert hist[0][1] < delta / 27
+    assert abs(hist[0][1] - delta / 50) <= 0.05 * delta / 50
+    assert hist[1][0] == hist[0][0] + delta / 10
+    assert delta / 27 <= hist[1][1] <= delta / 5
+    assert delta / 30 <= lam - lam1 <= 2 * delta / 9
+
+
+def test_rank_deficient_block_is_reported():
+    """rank(X) = 3 < p = 8: the estimate block loses rank and Cholesky-QR meets
+    a Gram matrix that is not positive definite."""
+    sig = np.zeros(64)
+    sig[:3] = [3.0, 2.0, 1.0]
+    X, _ = planted(64, 500, sig, 5)
+    with pytest.raises(LowRankError) as ei:
+        solve(np.ascontiguousarray(X.T), "f64", 2, 8, 1e-4, Options(seed=1))
+    assert ei.value.code == LR_ENOTSPD
