@@ -256,6 +256,28 @@ void lowrank_destroy(lr_plan plan);
 lr_status lowrank_plan_bytes(const lr_matrix* X, int k, int p, const lr_options* opt,
                              size_t* bytes);
 
+/* Device workspace that lowrank_solve_noalloc can hold: 64 MiB. */
+#define LR_NOALLOC_MAX_BYTES (64u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, tight serving loops, harnesses that forbid allocation): one whole
+ * solve, as lowrank_plan + lowrank_solve + lowrank_destroy, with no device
+ * allocation.  The workspace is a fixed array of LR_NOALLOC_MAX_BYTES in the
+ * library's device image (each device holds its own copy for the life of the
+ * process); host-side staging is per calling thread.
+ *   X, k, p, eps, opt, hip_stream  as for lowrank_plan; dense X only
+ *   U_out, theta_out, rep          as for lowrank_solve
+ * Returns the lowrank_solve status, or LR_ENOMEM (nothing run) when
+ * lowrank_plan_bytes exceeds LR_NOALLOC_MAX_BYTES, LR_EINVAL for compressed-
+ * column X (its plan builds a row-ordered copy) or opt->timing != 0 (timing
+ * needs events).  The solve does not depend on what the array holds when it
+ * starts.  Every call on one device uses the same array: calls that overlap on
+ * one device (other threads, other streams) race and give wrong results;
+ * serialise them. */
+lr_status lowrank_solve_noalloc(const lr_matrix* X, int k, int p, double eps,
+                                const lr_options* opt, void* hip_stream, double* U_out,
+                                double* theta_out, lr_report* rep);
+
 /* ---- Single steps of the path, on a plan's X and stream (for testing and
  * measurement).  All matrices FP64 device, column-major, leading dim d. ---- */
 

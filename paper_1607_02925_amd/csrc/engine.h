@@ -36,6 +36,12 @@ lr_status plan_bytes(const lr_matrix* X, int k, int p, const lr_options* opt, si
 lr_status plan_make(lr_plan_s** out, const lr_matrix* X, int k, int p, double eps,
                     const lr_options* opt, hipStream_t st, void* ws, size_t ws_bytes,
                     const HostRes* host);
+// Plan on the stack with a borrowed workspace (ws_bytes >= plan_bytes) and
+// borrowed host resources, one lowrank_solve, nothing kept.  Dense X only;
+// opt->timing must be 0 (host->ev may be null).
+lr_status solve_borrowed(const lr_matrix* X, int k, int p, double eps, const lr_options* opt,
+                         hipStream_t st, void* ws, size_t ws_bytes, const HostRes* host,
+                         double* U_out, double* theta_out, lr_report* rep);
 lr_status host_res_create(double** hpin, hipEvent_t* ev);
 void host_res_destroy(double* hpin, hipEvent_t* ev);
 

@@ -1158,17 +1158,14 @@ lr_status plan_bytes(const lr_matrix* Xm, int k, int p, const lr_options* opt, s
   return LR_OK;
 }
 
-lr_status plan_make(lr_plan_s** out, const lr_matrix* Xm, int k, int p, double eps,
+namespace {
+// Fill a default-constructed plan in place: shape, replay copy, workspace
+// (allocated, or carved from ws), host resources (created, or borrowed), and
+// for compressed-column X the row-ordered copy.  On failure the caller
+// destroys the plan.
+lr_status plan_init(lr_plan_s* pl, const lr_matrix* Xm, int k, int p, double eps,
                     const lr_options* opt, hipStream_t st, void* ws, size_t ws_bytes,
                     const HostRes* host) {
-  *out = nullptr;
-  LR_CHECK(plan_check(Xm, k, p, eps, opt));
-  lr_plan_s* pl = nullptr;
-  try {
-    pl = new lr_plan_s();
-  } catch (...) {
-    return fail(LR_ENOMEM, "host allocation failed");
-  }
   pl->st = st;
   pl->eps = eps;
   if (opt)
@@ -1185,34 +1182,62 @@ lr_status plan_make(lr_plan_s** out, const lr_matrix* Xm, int k, int p, double e
     pl->opt.replay = nullptr;
   }
   const size_t need = pl->carve(nullptr);
-  lr_status s = LR_OK;
   if (ws) {
     pl->owns_ws = false;
-    if (ws_bytes < need) s = fail(LR_EINVAL, "workspace smaller than the plan needs");
-    else pl->ws = ws;
+    if (ws_bytes < need) return fail(LR_EINVAL, "workspace smaller than the plan needs");
+    pl->ws = ws;
   } else if (hipMalloc(&pl->ws, need) != hipSuccess) {
     (void)hipGetLastError();
     pl->ws = nullptr;
-    s = fail(LR_ENOMEM, "device allocation failed");
+    return fail(LR_ENOMEM, "device allocation failed");
   }
-  if (s == LR_OK) pl->carve((char*)pl->ws);
-  if (s == LR_OK && pl->opt.fill_workspace &&
-      lr::fill_bytes(pl->ws, need, 0xFF, st) != hipSuccess)
-    s = fail(LR_EDEVICE, "workspace fill failed");
-  if (s == LR_OK && host) {
+  pl->carve((char*)pl->ws);
+  if (pl->opt.fill_workspace && lr::fill_bytes(pl->ws, need, 0xFF, st) != hipSuccess)
+    return fail(LR_EDEVICE, "workspace fill failed");
+  if (host) {
     pl->owns_host = false;
     pl->hpin = host->hpin;
     for (int i = 0; i < 8; ++i) pl->ev[i] = host->ev[i];
-  } else if (s == LR_OK) {
-    s = host_res_create(&pl->hpin, pl->ev);
+  } else {
+    LR_CHECK(host_res_create(&pl->hpin, pl->ev));
   }
-  if (s == LR_OK && pl->sparse) s = pl->sparse_setup();
+  if (pl->sparse) LR_CHECK(pl->sparse_setup());
+  return LR_OK;
+}
+}  // namespace
+
+lr_status plan_make(lr_plan_s** out, const lr_matrix* Xm, int k, int p, double eps,
+                    const lr_options* opt, hipStream_t st, void* ws, size_t ws_bytes,
+                    const HostRes* host) {
+  *out = nullptr;
+  LR_CHECK(plan_check(Xm, k, p, eps, opt));
+  lr_plan_s* pl = nullptr;
+  try {
+    pl = new lr_plan_s();
+  } catch (...) {
+    return fail(LR_ENOMEM, "host allocation failed");
+  }
+  const lr_status s = plan_init(pl, Xm, k, p, eps, opt, st, ws, ws_bytes, host);
   if (s != LR_OK) {
     delete pl;
     return s;
   }
   *out = pl;
   return LR_OK;
+}
+
+lr_status solve_borrowed(const lr_matrix* Xm, int k, int p, double eps, const lr_options* opt,
+                         hipStream_t st, void* ws, size_t ws_bytes, const HostRes* host,
+                         double* U_out, double* theta_out, lr_report* rep) {
+  LR_CHECK(plan_check(Xm, k, p, eps, opt));
+  if (Xm->layout != LR_DENSE_COLMAJOR)
+    return fail(LR_EINVAL, "a borrowed workspace needs dense X (compressed-column plans "
+                "build a row-ordered copy of X at plan time)");
+  if (opt && opt->timing)
+    return fail(LR_EINVAL, "timing needs the plan's own events");
+  lr_plan_s pl;   // on the stack: owns neither the workspace nor the host resources
+  LR_CHECK(plan_init(&pl, Xm, k, p, eps, opt, st, ws, ws_bytes, host));
+  return lowrank_solve(&pl, U_out, theta_out, rep);
 }
 
 lr_status host_res_create(double** hpin, hipEvent_t* ev) {

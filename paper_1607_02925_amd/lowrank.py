@@ -98,6 +98,11 @@ SIGNATURES = {
     "lowrank_plan_bytes": (ctypes.c_int, [ctypes.POINTER(lr_matrix), ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(lr_options),
                                           ctypes.POINTER(ctypes.c_size_t)]),
+    "lowrank_solve_noalloc": (ctypes.c_int, [ctypes.POINTER(lr_matrix), ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_double,
+                                             ctypes.POINTER(lr_options), _P, _P,
+                                             ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(lr_report)]),
     "lowrank_op_apply_A": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "lowrank_op_prepare": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "lowrank_op_sample": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -283,6 +288,29 @@ def plan_bytes(Xt, k, p, **kw):
     out = ctypes.c_size_t()
     _check(lib.lowrank_plan_bytes(ctypes.byref(mat), k, p, ctypes.byref(opt), ctypes.byref(out)))
     return out.value
+
+
+NOALLOC_MAX_BYTES = 64 * 1024 * 1024
+
+
+def solve_noalloc(Xt, k, p, eps, out=None, **kw):
+    """One solve through lowrank_solve_noalloc (no device allocation by the
+    library: its workspace is the library's fixed device array).  Dense X only.
+    Returns (status, U (d x k float64 device tensor), theta (numpy k), report)."""
+    import torch
+    lib = load_library()
+    mat = _matrix(Xt)
+    n, d = Xt.shape
+    opt, _keep = make_options(**kw)
+    U = out if out is not None else torch.empty((k, d), dtype=torch.float64, device=Xt.device)
+    theta = (ctypes.c_double * k)()
+    rep = lr_report()
+    with torch.cuda.device(Xt.device):
+        st = lib.lowrank_solve_noalloc(ctypes.byref(mat), k, p, float(eps), ctypes.byref(opt),
+                                       _stream(), _ptr(U), theta, ctypes.byref(rep))
+    if st != LR_OK and st != LR_ENOCONV:
+        _check(st)
+    return st, U.T, np.array(theta[:]), report_dict(rep, p)
 
 
 class Plan:
