@@ -141,6 +141,19 @@ typedef struct lr_schedule {
  *                   the sampled products; the difference itself is kept and
  *                   updated in FP64, and everything outside the steps stays FP64
  *                   as above.  Same agreement as the BF16 form.
+ *                   LR_PREC_MC_PASS (dense FP32 or BF16 X with ld % 8 == 0 and
+ *                   a 16-byte aligned base, else LR_EINVAL): the full-gradient
+ *                   passes of the shift-and-invert solves run on BF16 matrix
+ *                   cores.  W and T = X^T W are carried as three BF16 parts
+ *                   (24 significant bits), FP32 X as three parts (exact), BF16 X
+ *                   as itself; products of parts with index sum below three are
+ *                   accumulated in FP32 and added into FP64 every 256 terms.
+ *                   The estimate phase, shift tuning, Cholesky-QR and the final
+ *                   Rayleigh-Ritz stay FP64; inner steps FP64.
+ *                   LR_PREC_MC: matrix-core passes as LR_PREC_MC_PASS and
+ *                   matrix-core inner steps (the BF16 form for BF16 X, the FP32
+ *                   form for FP32 X).  Results of both agree with the FP64 form
+ *                   to the accuracy the passes carry, not bit for bit.
  *   adaptive        0 (default): the q = k branch of Algorithm "main" (one
  *                   shift-and-invert iteration with oversampling).  1: the
  *                   adaptive partitioning of Algorithm "main" (Section 3.2):
@@ -173,7 +186,13 @@ typedef struct lr_schedule {
  *                   (with the strong-convexity estimate max(lambda - theta_1 -
  *                   ||r_1||, Delta/30)) instead of the start shift_mode names;
  *                   0 (default): shift_mode decides. */
-typedef enum { LR_PREC_F64 = 0, LR_PREC_BF16_STEPS = 1, LR_PREC_F32_STEPS = 2 } lr_precision;
+typedef enum {
+  LR_PREC_F64 = 0,
+  LR_PREC_BF16_STEPS = 1,
+  LR_PREC_F32_STEPS = 2,
+  LR_PREC_MC_PASS = 3,
+  LR_PREC_MC = 4
+} lr_precision;
 
 typedef struct lr_options {
   uint64_t seed;
@@ -220,6 +239,7 @@ typedef struct lr_report {
   int32_t interval_s[LR_MAX_P], interval_q[LR_MAX_P], interval_branch[LR_MAX_P];
   int32_t interval_cols[LR_MAX_P], interval_iters[LR_MAX_P];
   double accel_kappa, accel_beta; /* accel = 1: kappa and beta of the last solve's schedule */
+  int64_t mc_passes;              /* passes run on matrix cores (LR_PREC_MC_PASS, LR_PREC_MC) */
 } lr_report;
 
 typedef struct lr_plan_s* lr_plan;
@@ -282,7 +302,9 @@ lr_status lowrank_solve_noalloc(const lr_matrix* X, int k, int p, double eps,
  * measurement).  All matrices FP64 device, column-major, leading dim d. ---- */
 
 /* Y = X (X^T W) for a d x ncols block W (ncols <= p); A = XX^T is never
- * formed (Section 2.2.1, footnote). */
+ * formed (Section 2.2.1, footnote).  Computed as the plan's solves compute
+ * their passes: on matrix cores for LR_PREC_MC_PASS and LR_PREC_MC, else FP64.
+ * lowrank_op_svrg_solve and lowrank_op_acc_svrg_solve likewise. */
 lr_status lowrank_op_apply_A(lr_plan plan, const double* W, double* Y, int ncols);
 
 /* Plan step a0: column squared norms w (n), quantised cumulative table

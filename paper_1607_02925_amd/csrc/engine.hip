@@ -19,6 +19,7 @@
 #include "bf16.h"
 #include "f32steps.h"
 #include "kernels.h"
+#include "mcpass.h"
 #include "sparse.h"
 
 namespace {
@@ -76,6 +77,10 @@ struct lr_plan_s {
   // ranges, each pad16(bmax) x PC)
   bool f32_steps = false;
   float *D32 = nullptr, *C32 = nullptr;
+  // matrix-core passes (FP32 / BF16 X): BF16 parts of W and T, FP32 partial
+  // sums; used by the passes of the shift-and-invert solves while mc_active
+  bool mc_pass = false, mc_active = false;
+  lr::McBufs mb{};
   // adaptive partitioning (Algorithm "main"): the deflation basis Ud (d x ns),
   // Z = X^T Ud (n x pad16(ns) row-major), projection temporaries, the chunk
   // partials of the deflated inner step
@@ -183,6 +188,12 @@ struct lr_plan_s {
       rep.passes++;
       return LR_OK;
     }
+    if (mc_active && !sparse) {
+      LR_HIP(lr::mc_pass(X, Win, ncols, PC, mb, alpha, A, beta, B, gamma, Yout, st));
+      rep.passes++;
+      rep.mc_passes++;
+      return LR_OK;
+    }
     LR_CHECK(xtw(Win, ncols));
     if (sparse)
       LR_HIP(lr::csr_xt(R, T, PC, ncols, sp_part, alpha, A, beta, B, gamma, Yout, st));
@@ -285,8 +296,14 @@ struct lr_plan_s {
       df.Ud = Ud;
       df.Vp = Vp;
     }
-    // warm start W0 = S (lam I - S^T A S)^{-1}; its gradient costs no extra pass
-    LR_CHECK(applyA(Srhs, Y, pc));
+    // warm start W0 = S (lam I - S^T A S)^{-1}; its gradient costs no extra pass.
+    // With matrix-core passes this pass stays FP64 and each epoch's pass is
+    // applied to the epoch's step difference only (see the epoch update below).
+    const bool mc = mc_active && !accel && ns == 0;
+    mc_active = false;
+    const lr_status s0 = applyA(Srhs, Y, pc);
+    mc_active = mc;
+    LR_CHECK(s0);
     LR_CHECK(gram_dd(Srhs, pc, Y, pc, H));
     LR_HIP(lr::eigh(H, pc, vals, Q, st));
     LR_HIP(lr::shift_inverse(vals, Q, pc, lam, M, st));
@@ -392,6 +409,20 @@ struct lr_plan_s {
         LR_HIP(lr::lincomb(cnt, 1.0, G, -kappa, Ynew, kappa, Yk, G, st));
         std::swap(Yk, Ynew);
         std::swap(Wt, Wn);
+      } else if (mc) {
+        // residual refinement: G~ is linear in W~, so the new anchor's gradient is
+        // the old one plus lam D - X X^T D for the epoch's difference D = W~' - W~;
+        // the matrix-core pass then errs relative to D rather than to W~
+        if (tiled)
+          LR_HIP(lr::tile_add(d, pc, PCn, Wt, Dl, Tm1, st));
+        else
+          LR_HIP(lr::lincomb(cnt, 1.0, Wt, 1.0, Dl, 0.0, nullptr, Tm1, st));
+        LR_HIP(lr::lincomb(cnt, 1.0, Tm1, -1.0, Wt, 0.0, nullptr, Tm2, st));
+        if (opt.timing) LR_HIP(hipEventRecord(ev[2], st));
+        LR_CHECK(applyA(Tm2, G, pc, -1.0, Tm2, lam, G, 1.0));
+        if (opt.timing) LR_HIP(hipEventRecord(ev[3], st));
+        LR_HIP(hipMemcpyAsync(Wt, Tm1, cnt * sizeof(double), hipMemcpyDeviceToDevice, st));
+        LR_HIP(lr::sumsq(G, cnt, part, dnorm, st));
       } else {
         if (tiled)
           LR_HIP(lr::tile_add(d, pc, PCn, Wt, Dl, Wt, st));
@@ -583,9 +614,13 @@ lr_status lr_plan_s::solve(double* U_out, double* theta_out, lr_report* out_rep)
   double change = -1.0;
   for (int ell = 0; ell < L; ++ell) {
     int32_t e = 0;
-    LR_CHECK(svrg_solve(S, sched.lambda, sched.eta, sched.m, sched.b, sched.first_solve + ell,
-                        sched.tau, replay ? repochs[ell] : -1, &e, nullptr, -1, acc_kappa,
-                        acc_beta));
+    mc_active = mc_pass;
+    const lr_status si = svrg_solve(S, sched.lambda, sched.eta, sched.m, sched.b,
+                                    sched.first_solve + ell, sched.tau,
+                                    replay ? repochs[ell] : -1, &e, nullptr, -1, acc_kappa,
+                                    acc_beta);
+    mc_active = false;
+    LR_CHECK(si);
     epochs.push_back(e);
     LR_CHECK(gram_dd(S, p, Wt, p, H));
     LR_HIP(lr::eigh(H, p, vals, Q, st));
@@ -875,6 +910,15 @@ size_t lr_plan_s::carve(char* base) {
   take(&Vp, adaptive ? (int64_t)lr::zbc_chunks(bmax) * 64 * 64 : 0);
   for (uint16_t** b : {&Ch, &Cl}) take(b, bf16_steps ? ldC * PC : 0);
   take(&D32, f32_steps ? lr::pad16(d) * PC : 0);
+  {
+    const lr::McSizes z = mc_pass ? lr::mc_sizes(d, n, PC) : lr::McSizes{0, 0, 0, 0};
+    take(&mb.Wp, z.wp_elems);
+    take(&mb.Tp, z.tp_elems);
+    take(&mb.part, z.part_elems);
+    mb.wstride = z.wp_elems / 3;
+    mb.tstride = z.tp_elems / 3;
+    mb.nsplit = z.nsplit;
+  }
   take(&C32, f32_steps ? 2 * lr::pad16(bmax) * PC : 0);   // two row-split partials
   take(&T, n * PC);
   take(&Ypart, (int64_t)pb.nsplit * dp);
@@ -1084,8 +1128,13 @@ lr_status plan_check(const lr_matrix* Xm, int k, int p, double eps, const lr_opt
   if (!(eps > 0)) return fail(LR_EINVAL, "eps must be positive");
   if (opt) {
     if (opt->batch < 0 || opt->batch > 8192) return fail(LR_EINVAL, "batch must be in [0, 8192]");
-    if (opt->precision < LR_PREC_F64 || opt->precision > LR_PREC_F32_STEPS)
+    if (opt->precision < LR_PREC_F64 || opt->precision > LR_PREC_MC)
       return fail(LR_EINVAL, "unknown precision");
+    if ((opt->precision == LR_PREC_MC_PASS || opt->precision == LR_PREC_MC) &&
+        (Xm->layout != LR_DENSE_COLMAJOR || Xm->dtype == LR_F64 || Xm->ld % 8 ||
+         (uintptr_t)Xm->values % 16))
+      return fail(LR_EINVAL, "matrix-core passes need dense FP32 or BF16 X with ld a multiple "
+                  "of 8 and a 16-byte aligned base");
     if (opt->precision == LR_PREC_BF16_STEPS &&
         (Xm->layout != LR_DENSE_COLMAJOR || Xm->dtype != LR_BF16))
       return fail(LR_EINVAL, "BF16 matrix-core steps need dense BF16 X");
@@ -1127,8 +1176,10 @@ void plan_shape(lr_plan_s* pl, const lr_matrix* Xm, int k, int p, const lr_optio
   pl->bmax = std::min<int64_t>(Xm->n, 8192);
   pl->PC = lr::pad16(p);
   pl->pb.nsplit = pl->sparse ? 0 : lr::pass_nsplit(Xm->d, Xm->n);
-  pl->bf16_steps = opt && opt->precision == LR_PREC_BF16_STEPS;
-  pl->f32_steps = opt && opt->precision == LR_PREC_F32_STEPS;
+  const int prec = opt ? opt->precision : LR_PREC_F64;
+  pl->mc_pass = prec == LR_PREC_MC_PASS || prec == LR_PREC_MC;
+  pl->bf16_steps = prec == LR_PREC_BF16_STEPS || (prec == LR_PREC_MC && Xm->dtype == LR_BF16);
+  pl->f32_steps = prec == LR_PREC_F32_STEPS || (prec == LR_PREC_MC && Xm->dtype == LR_F32);
   pl->adaptive = opt && opt->adaptive == 1;
   pl->accel = opt && opt->accel == 1;
   pl->ldD = lr::pad_to(Xm->d, 32);
@@ -1344,7 +1395,10 @@ void lowrank_destroy(lr_plan plan) { delete plan; }
 
 lr_status lowrank_op_apply_A(lr_plan plan, const double* W, double* Y, int ncols) {
   if (!plan || !W || !Y || ncols < 1 || ncols > plan->p) return fail(LR_EINVAL, "bad argument");
-  LR_CHECK(plan->applyA(W, Y, ncols));
+  plan->mc_active = plan->mc_pass;
+  const lr_status s = plan->applyA(W, Y, ncols);
+  plan->mc_active = false;
+  LR_CHECK(s);
   LR_HIP(hipStreamSynchronize(plan->st));
   return LR_OK;
 }
@@ -1458,7 +1512,10 @@ lr_status lowrank_op_svrg_solve(lr_plan plan, const double* S, double lambda, do
   if (!plan->prepared) return fail(LR_EINVAL, "call lowrank_op_prepare first");
   std::vector<double> hist;
   int32_t e = 0;
-  LR_CHECK(plan->svrg_solve(S, lambda, eta, m, b, solve, 0.0, epochs, &e, &hist));
+  plan->mc_active = plan->mc_pass;
+  const lr_status s = plan->svrg_solve(S, lambda, eta, m, b, solve, 0.0, epochs, &e, &hist);
+  plan->mc_active = false;
+  LR_CHECK(s);
   LR_HIP(hipMemcpyAsync(W_out, plan->Wt, plan->d * plan->p * sizeof(double),
                         hipMemcpyDeviceToDevice, plan->st));
   LR_HIP(hipStreamSynchronize(plan->st));
@@ -1477,7 +1534,11 @@ lr_status lowrank_op_acc_svrg_solve(lr_plan plan, const double* S, double lambda
   if (!plan->prepared) return fail(LR_EINVAL, "call lowrank_op_prepare first");
   std::vector<double> hist;
   int32_t e = 0;
-  LR_CHECK(plan->svrg_solve(S, lambda, eta, m, b, solve, 0.0, epochs, &e, &hist, -1, kappa, beta));
+  plan->mc_active = plan->mc_pass;
+  const lr_status s =
+      plan->svrg_solve(S, lambda, eta, m, b, solve, 0.0, epochs, &e, &hist, -1, kappa, beta);
+  plan->mc_active = false;
+  LR_CHECK(s);
   LR_HIP(hipMemcpyAsync(W_out, plan->Wt, plan->d * plan->p * sizeof(double),
                         hipMemcpyDeviceToDevice, plan->st));
   LR_HIP(hipStreamSynchronize(plan->st));

@@ -19,7 +19,7 @@ LR_MAX_P = 64
 LR_MAX_SHIFT_ROUNDS = 64
 LR_MAX_SLOTS = 16
 LR_F64, LR_F32, LR_BF16 = 0, 1, 2
-LR_PREC_F64, LR_PREC_BF16_STEPS, LR_PREC_F32_STEPS = 0, 1, 2
+LR_PREC_F64, LR_PREC_BF16_STEPS, LR_PREC_F32_STEPS, LR_PREC_MC_PASS, LR_PREC_MC = 0, 1, 2, 3, 4
 
 
 class lr_matrix(ctypes.Structure):
@@ -66,7 +66,8 @@ class lr_report(ctypes.Structure):
                 ("interval_branch", ctypes.c_int32 * LR_MAX_P),
                 ("interval_cols", ctypes.c_int32 * LR_MAX_P),
                 ("interval_iters", ctypes.c_int32 * LR_MAX_P),
-                ("accel_kappa", ctypes.c_double), ("accel_beta", ctypes.c_double)]
+                ("accel_kappa", ctypes.c_double), ("accel_beta", ctypes.c_double),
+                ("mc_passes", ctypes.c_int64)]
 
 
 class lr_ticket_info(ctypes.Structure):
@@ -557,4 +558,5 @@ def report_dict(rep, p):
                        "cols": rep.interval_cols[i], "iters": rep.interval_iters[i]}
                       for i in range(min(rep.n_intervals, LR_MAX_P))],
         "accel_kappa": rep.accel_kappa, "accel_beta": rep.accel_beta,
+        "mc_passes": rep.mc_passes,
     }
