@@ -53,9 +53,10 @@ def parse():
     ap.add_argument("--sparse-workload", default=SPARSE_WORKLOAD)
     ap.add_argument("--sparse-steps", type=int, default=200,
                     help="sparse/steps: inner steps timed (one epoch of this length)")
-    ap.add_argument("--precision", type=int, default=0,
+    ap.add_argument("--precision", type=int, default=4,
                     help="0: FP64 arithmetic; 1: BF16 matrix-core inner steps (BF16 X); "
-                         "2: FP32 matrix-core inner steps (FP32 or BF16 X)")
+                         "2: FP32 matrix-core inner steps (FP32 or BF16 X); 3: matrix-core "
+                         "passes; 4 (default): matrix-core passes and inner steps")
     ap.add_argument("--batch", type=int, default=0, help="steps: minibatch size (0: 4096)")
     ap.add_argument("--adaptive", type=int, default=0,
                     help="solve: 1 = adaptive partitioning of Algorithm main")
@@ -74,6 +75,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true",
                     help="solve mode: skip the serving legs of the report")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="solve mode: skip the 4096 x 500000 BF16 and compressed-column legs")
     return ap.parse_args()
 
 
@@ -86,19 +89,31 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (pos - lo)
 
 
+# kernel -> the source file whose SHA-256 a committed counter summary must match
+KERNEL_SOURCES = {
+    "k_step_update": "kernels.hip", "k_xtm_gathered": "kernels.hip",
+    "k_xtm_pass": "kernels.hip", "k_xt_part": "kernels.hip",
+    "k_supd_f32": "f32steps.hip", "k_sdot_f32": "f32steps.hip",
+    "k_supd_bf16": "bf16.hip", "k_sdot_bf16": "bf16.hip",
+    "k_mc_xtw": "mcpass.hip", "k_mc_xt": "mcpass.hip",
+}
+
+
 def measured_traffic(kernel, workload):
     """Calibrated HBM bytes per launch of `kernel` from the committed rocprofv3
-    counter summary, or None when the kernels have changed since it was taken."""
+    counter summary, or None when the kernel's source has changed since it was
+    taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_%s.md" % workload)
-    src = os.path.join(ROOT, "paper_1607_02925_amd", "csrc", "kernels.hip")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
         return None
+    src = os.path.join(ROOT, "paper_1607_02925_amd", "csrc", KERNEL_SOURCES[kernel])
     text = open(path).read()
     if "```json" not in text:
         return None
     t = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != t["kernels_sha256"]:
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if t.get("sources_sha256", {}).get(KERNEL_SOURCES[kernel]) != sha:
         return None
     k = t["per_launch_kib"].get(kernel)
     if k is None:
@@ -180,8 +195,9 @@ def variant_leg(Xt, w, U_qk, args, name, **kw):
 def serve_run(reqs, X, slots, budget, open_loop=False, matrix_core=False):
     """Push every request of `reqs` (device matrices X[i]) through a server with
     `slots` worker slots and an HBM budget; closed loop submits all at t = 0,
-    open loop at each request's arrival time.  matrix_core: inner steps on
-    matrix cores (BF16 steps for BF16 X, FP32 steps for FP32 X) instead of FP64.
+    open loop at each request's arrival time.  matrix_core: passes and inner
+    steps on matrix cores (LR_PREC_MC: BF16-part passes with refined residuals,
+    BF16 steps for BF16 X, FP32 steps for FP32 X) instead of FP64.
     Returns per-request results."""
     import torch
     from paper_1607_02925_amd import lowrank
@@ -194,9 +210,7 @@ def serve_run(reqs, X, slots, budget, open_loop=False, matrix_core=False):
             delay = r["arrival"] - (time.time() - t0)
             if delay > 0:
                 time.sleep(delay)
-        prec = 0
-        if matrix_core:
-            prec = 1 if x.dtype == torch.bfloat16 else 2
+        prec = 4 if matrix_core else 0
         tickets.append(srv.submit(x, r["k"], r["p"], r["eps"], sync=False,
                                   seed=r["solver_seed"], precision=prec))
     outs = [srv.wait(t) for t in tickets]
@@ -314,6 +328,59 @@ def steps_bench(args, dev):
     return out
 
 
+def big_dense_leg(args, dev, name):
+    """A dense workload too large for a whole solve per bench step: its pass in
+    FP64 and on matrix cores (roofline on |X| + 3 d p 4 bytes) and an epoch of
+    matrix-core inner steps at the minibatch the method picks for it (b = 4096),
+    with a shift 5% above the top Ritz value of six power steps."""
+    import torch
+    import workloads
+    from paper_1607_02925_amd import lowrank
+    w = dict(workloads.WORKLOADS[name])
+    data = workloads.workload(name, device=dev)
+    Xt = data["Xt"]
+    torch.cuda.synchronize()
+    d, n, p = w["d"], w["n"], w["p"]
+    x_bytes = Xt.numel() * Xt.element_size()
+    out = {"workload": name, "d": d, "n": n, "p": p}
+    W = torch.randn((p, d), dtype=torch.float64, device=dev).T
+    for prec, key in ((0, "pass_f64"), (3, "pass_mc")):
+        plan = lowrank.Plan(Xt, w["k"], p, w["eps"], seed=w["solver_seed"], precision=prec)
+        plan.apply_A(W)
+        torch.cuda.synchronize()
+        reps = max(3, args.steps)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            plan.apply_A(W)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        gbs = (x_bytes + 3 * d * p * 4) / (ms * 1e-3) / 1e9
+        out[key] = {"ms": ms, "hbm_GBps_alg": gbs, "frac_hbm": gbs / PEAK_HBM_GBS}
+        del plan
+    plan = lowrank.Plan(Xt, w["k"], p, w["eps"], seed=w["solver_seed"], precision=4)
+    _, _, fro2 = plan.prepare()
+    S = torch.linalg.qr(torch.randn((d, p), dtype=torch.float64, device=dev))[0]
+    for _ in range(6):
+        S = torch.linalg.qr(plan.apply_A(S))[0]
+    theta1 = float(torch.linalg.eigvalsh(S.T @ plan.apply_A(S))[-1])
+    lam, mu, b = 1.05 * theta1, 0.05 * theta1, 4096
+    eta = min(1.0 / lam, mu * b / (4.0 * fro2 * theta1))
+    m = 200
+    plan.svrg_solve(S, lam, eta, 8, b, 1, 1)
+    torch.cuda.synchronize()
+    t = time.time()
+    plan.svrg_solve(S, lam, eta, m, b, 2, 1)
+    torch.cuda.synchronize()
+    ms_epoch = (time.time() - t) * 1e3
+    out["epoch_mc"] = {"b": b, "steps": m, "epoch_ms": ms_epoch,
+                       "step_us": (ms_epoch - out["pass_f64"]["ms"] - out["pass_mc"]["ms"])
+                       / m * 1e3}
+    log("%s: %s" % (name, json.dumps(out)))
+    return out
+
+
 def lowrank_pad16(p):
     return (p + 15) // 16 * 16
 
@@ -358,9 +425,9 @@ def serve_bench(args, dev):
                     float(torch.linalg.matrix_norm(Ub - Ua @ (Ua.T @ Ub), ord=2)))
             out["batched_closed_matrix_core"]["max_sin_vs_fp64_steps"] = {
                 k: max(v) if v else None for k, v in sins.items()}
-            out["matrix_core_agrees"] = all(v is None or v <= 1e-10 for v in
-                                            out["batched_closed_matrix_core"]
-                                            ["max_sin_vs_fp64_steps"].values())
+            out["matrix_core_agrees"] = all(
+                v is None or v <= (1e-6 if kk == "f32" else 1e-3) for kk, v in
+                out["batched_closed_matrix_core"]["max_sin_vs_fp64_steps"].items())
         log("serve batched closed loop, matrix-core steps: %s" %
             json.dumps(out["batched_closed_matrix_core"]))
     if seq_outs is not None and closed_outs is not None:
@@ -495,11 +562,20 @@ def main():
     sched = plan.schedule()
     rep = reps[-1]
 
-    # dominant kernel: the per-step update (gathers b columns, updates the d x p difference)
+    # dominant kernel among the inner-step pair (each gathers b columns of X)
     sx = Xt.element_size()
     b = sched.b
-    bytes_update = b * d * sx + b * p * 8 + 3 * d * p * 8
-    bytes_sdot = b * d * sx + d * p * 8 + b * p * (8 + 8) + b * 4
+    PCw = lowrank_pad16(p)
+    if args.precision in (0, 3):
+        names = ("k_step_update", "k_xtm_gathered")
+        bytes_update = b * d * sx + b * PCw * 8 + 3 * d * p * 8
+        bytes_sdot = b * d * sx + d * PCw * 8 + b * PCw * 8 + b * 12
+    else:
+        form = "bf16" if (args.precision == 1 or (args.precision == 4 and sx == 2)) else "f32"
+        names = ("k_supd_" + form, "k_sdot_" + form)
+        cb = 4 if form == "f32" else 4          # C as FP32 (or two BF16 parts)
+        bytes_update = b * d * sx + b * PCw * cb + 3 * d * p * 8 + d * PCw * cb
+        bytes_sdot = b * d * sx + d * PCw * cb + b * PCw * cb + b * 12
     probes = sum(r["probes"] for r in reps)
     ms_upd = sum(r["ms_update_probe"] for r in reps) / max(probes, 1)
     ms_sdot = sum(r["ms_sample_dot_probe"] for r in reps) / max(probes, 1)
@@ -508,14 +584,19 @@ def main():
     t_sdot_total = ms_sdot * rep["steps"]
     t_pass_total = ms_pass * rep["passes"]
     kernels = {
-        "k_step_update": (t_upd_total, bytes_update, ms_upd),
-        "k_xtm_gathered": (t_sdot_total, bytes_sdot, ms_sdot),
+        names[0]: (t_upd_total, bytes_update, ms_upd),
+        names[1]: (t_sdot_total, bytes_sdot, ms_sdot),
     }
     dom = max(kernels, key=lambda kk: kernels[kk][0])
     _, dbytes, dms = kernels[dom]
     achieved = dbytes / (dms * 1e-3) / 1e9 if dms > 0 else None
-    pass_gbs = x_bytes / (ms_pass * 1e-3) / 1e9 if ms_pass > 0 else None
-    pass_tflops = 4.0 * d * n * p / (ms_pass * 1e-3) / 1e12 if ms_pass > 0 else None
+    # the pass: |X| + 3 d p 4 algorithmic bytes (X once, W~ and S in, G~ out)
+    pass_bytes = x_bytes + 3 * d * p * 4
+    pass_gbs = pass_bytes / (ms_pass * 1e-3) / 1e9 if ms_pass > 0 else None
+    mc = args.precision in (3, 4)
+    dtype = {0: "f64", 1: "f64+bf16-steps", 2: "f64+f32-steps",
+             3: "bf16x3-passes(f32-acc)+f64",
+             4: "bf16x3-passes(f32-acc)+%s-steps+f64" % ("bf16" if sx == 2 else "f32")}
     out = {
         "metric": METRIC,
         "value": args.steps / total,
@@ -527,17 +608,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == 0 else "f64+f32-steps" if args.precision == 2
-                 else "f64+bf16-steps",
+        "dtype": dtype.get(args.precision, "f64"),
         "data": "synthetic planted-spectrum matrix generated on the GPU from fixed seeds",
         "config": {"workload": args.workload, "d": d, "n": n, "k": k, "p": p, "eps": w["eps"],
-                   "storage": w["storage"], "form": "per-request",
+                   "storage": w["storage"], "form": "per-request", "precision": args.precision,
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": percentile(lat, 0.5) * 1e3, "p99": percentile(lat, 0.99) * 1e3},
-        "pass": {"ms": ms_pass, "hbm_GBps_alg": pass_gbs, "fp64_TFLOPs": pass_tflops,
-                 "frac_hbm": pass_gbs / PEAK_HBM_GBS if pass_gbs else None},
+        "pass": {"kernels": "k_mc_split_w + k_mc_xtw + k_mc_xt + k_mc_reduce" if mc
+                 else "k_cm_to_tile + k_xtm + k_xt_part + k_reduce_y",
+                 "ms": ms_pass, "bytes_alg": pass_bytes, "hbm_GBps_alg": pass_gbs,
+                 "frac_hbm": pass_gbs / PEAK_HBM_GBS if pass_gbs else None,
+                 "x_reads_per_pass": 2},
         "solve": {"status": st, "outer": rep["outer"], "epochs": rep["total_epochs"],
-                  "passes": rep["passes"], "inner_steps": rep["steps"],
+                  "passes": rep["passes"], "mc_passes": rep["mc_passes"],
+                  "inner_steps": rep["steps"],
                   "shift_rounds": rep["shift_rounds"], "lambda": sched.lam, "m": sched.m,
                   "b": sched.b, "share_update": t_upd_total / (total / args.steps * 1e3),
                   "share_sample_dot": t_sdot_total / (total / args.steps * 1e3),
@@ -548,21 +632,28 @@ def main():
                      "bytes_per_launch": dbytes, "avg_launch_ms": dms},
         "cpu_baseline": None,
     }
-    if args.adaptive or args.accel or args.precision:
-        out["config"]["variant"] = {"adaptive": args.adaptive, "accel": args.accel,
-                                    "precision": args.precision}
+    if args.adaptive or args.accel:
+        out["config"]["variant"] = {"adaptive": args.adaptive, "accel": args.accel}
     elif not args.no_variants:
+        if args.precision != 0:
+            out["f64"] = variant_leg(Xt, w, U, args, "f64", precision=0)
+        if args.precision != 2 and Xt.dtype != torch.float64:
+            out["f32_steps"] = variant_leg(Xt, w, U, args, "f32-steps", precision=2)
         out["adaptive"] = variant_leg(Xt, w, U, args, "adaptive", adaptive=1)
         out["accel"] = variant_leg(Xt, w, U, args, "accel", accel=1)
         out["adaptive_accel"] = variant_leg(Xt, w, U, args, "adaptive+accel", adaptive=1,
                                             accel=1)
-        if Xt.dtype != torch.float64:
-            out["f32_steps"] = variant_leg(Xt, w, U, args, "f32-steps", precision=2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Xt, dict(w, **data), sched, rep)
-    if not args.no_serve:
+    if not args.no_legs or not args.no_serve:
         del Xt, data, plan
         torch.cuda.empty_cache()
+    if not args.no_legs:
+        out["bf16_4096x500000"] = big_dense_leg(args, dev, "planted-4096x500000-bf16")
+        torch.cuda.empty_cache()
+        out["csc_50000x1000000"] = sparse_bench(args, dev)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
         out["serve"] = serve_bench(args, dev)
     print(json.dumps(out), flush=True)
     serve_consistency_exit(out.get("serve"))

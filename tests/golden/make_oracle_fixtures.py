@@ -24,6 +24,7 @@ import workloads  # noqa: E402
 FIXTURES = {
     "planted-256x8192-f32": None,
     "planted-512x16384-bf16": 3,
+    "planted-2048x200000-f32": None,
 }
 
 

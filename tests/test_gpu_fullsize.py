@@ -63,6 +63,26 @@ def test_full_size_table_and_pass(torch_cuda, name):
     rel = np.linalg.norm(Y - Yo) / np.linalg.norm(Yo)
     print("%s: table bit-exact, pass rel err %.2e" % (name, rel), flush=True)
     assert rel <= 1e-13
+    # elementwise against each entry's own scale: the pass in FP64 errs by a few
+    # (n + d) 2^-53 of |X| (|X|^T |W|); here bounded through |Y_r| sums of
+    # column magnitudes, sampled rows (the full |X| product is a pass itself)
+    Wa = np.abs(W)
+    Yb = np.zeros_like(Y)
+    for c0 in range(0, w["n"], CHUNK):
+        Xc = np.abs(host_columns(w["Xt"], w["storage"], c0, min(w["n"], c0 + CHUNK)))
+        Yb += Xc @ (Xc.T @ Wa)
+        del Xc
+    assert np.all(np.abs(Y - Yo) <= 4 * (w["n"] + w["d"]) * 2.0 ** -53 * Yb)
+    # the matrix-core pass on the same X and W, elementwise against the same bound
+    plan_mc = lowrank.Plan(w["Xt"], w["k"], w["p"], w["eps"], seed=w["solver_seed"],
+                           precision=lowrank.LR_PREC_MC_PASS)
+    Ym = plan_mc.apply_A(torch.from_numpy(W).cuda()).cpu().numpy()
+    err_mc = np.abs(Ym - Yo)
+    rel_mc = np.linalg.norm(Ym - Yo) / np.linalg.norm(Yo)
+    print("%s: matrix-core pass rel err %.2e, max err / bound %.2e" %
+          (name, rel_mc, float(np.max(err_mc / Yb))), flush=True)
+    assert np.all(err_mc <= 2e-5 * Yb)
+    assert rel_mc <= 1e-6
 
 
 @pytest.mark.parametrize("precision", [0, 2])
@@ -80,7 +100,9 @@ def test_full_size_epoch_bench_schedule(torch_cuda, precision):
                         precision=precision)
     wg, _, _ = plan.prepare()
     X = host_columns(w["Xt"], w["storage"], 0, w["n"])      # 2048 x 200000 FP64
-    _, qc = oracle.build_table(wg.cpu().numpy())
+    wo = oracle.column_sq_norms(X)
+    assert np.array_equal(wg.cpu().numpy(), wo)
+    _, qc = oracle.build_table(wo)
     S = oracle.cholqr2(np.random.default_rng(5).standard_normal((w["d"], w["p"])))[0]
     lam, eta, m, b = 101.64710238615051, 0.009837925024862453, 124, 2048
     Wg, res_g = plan.svrg_solve(torch.from_numpy(S).cuda(), lam, eta, m, b, 3, 1)

@@ -96,6 +96,10 @@ def test_apply_A(torch_cuda, storage, d, n, p):
     X = oracle.decode(xt, storage)
     ref = oracle.apply_A(X, W)
     assert np.linalg.norm(Y - ref) <= 1e-13 * np.linalg.norm(ref)
+    # elementwise: FP64 dot products of n and d terms err by at most a few
+    # (n + d) 2^-53 of the sum of their terms' magnitudes
+    bound = np.abs(X) @ (np.abs(X).T @ np.abs(W))
+    assert np.all(np.abs(Y - ref) <= 4 * (n + d) * 2.0 ** -53 * bound)
 
 
 def test_cholqr2_and_eigh(torch_cuda):
@@ -286,3 +290,35 @@ def test_error_statuses(torch_cuda):
     with pytest.raises(lowrank.LowRankError) as ei:
         plan.solve()
     assert ei.value.code == lowrank.LR_ESHIFT
+
+
+@pytest.mark.parametrize("name,prec", [("planted-256x2048-f64", 0), ("planted-256x8192-f32", 0),
+                                       ("planted-256x8192-f32", 4)])
+def test_frobenius_error_and_guarantee(torch_cuda, name, prec):
+    """Theorem "mainResult" on GPU results: the relative Frobenius error
+    ||X - U U^T X||_F of the GPU's U_k matches the oracle's to 1e-8 and stays
+    within (1 + eps) ||X - X_k||_F (X_k from a LAPACK SVD of the stored X)."""
+    from paper_1607_02925_amd import lowrank
+    if name == "planted-256x8192-f32":
+        w, Uo, _, _, _ = _fixture_or_oracle(name, None)
+    else:
+        w = workloads.workload(name)
+        Uo = oracle.solve(w["Xt"], w["storage"], w["k"], w["p"], w["eps"],
+                          oracle.Options(seed=w["solver_seed"])).U
+    X = oracle.decode(w["Xt"], w["storage"])
+    plan = plan_for(torch_cuda, w["Xt"], w["storage"], w["k"], w["p"], w["eps"],
+                    seed=w["solver_seed"], precision=prec)
+    st, U, _, _ = plan.solve()
+    assert st == 0
+    Ug = U.cpu().numpy()
+
+    def ferr(Uk):
+        return np.linalg.norm(X - Uk @ (Uk.T @ X))
+
+    e_g, e_o = ferr(Ug), ferr(Uo)
+    s = np.linalg.svd(X, compute_uv=False)
+    e_k = np.sqrt(np.sum(s[w["k"]:] ** 2))
+    print("%s precision %d: ||X - PX||_F gpu %.12e oracle %.12e best %.12e" %
+          (name, prec, e_g, e_o, e_k), flush=True)
+    assert abs(e_g - e_o) <= 1e-8 * e_o
+    assert e_g <= (1 + w["eps"]) * e_k
