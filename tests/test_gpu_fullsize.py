@@ -6,11 +6,17 @@ times, against the oracle:
   schedule a solve of this workload uses (m = 124 steps of b = 2048 samples),
   with FP64 and with FP32 matrix-core steps;
 * 4096 x 500000 bf16: the sampling table bit for bit and one whole pass at
-  p = 48, and a whole adaptive solve against the exact top-k subspace.
+  p = 48, and a whole adaptive solve against the exact top-k subspace;
+* whole solves of the 2048 x 200000 f32 workload (as the NumPy generator makes
+  it) against the stored full oracle run on the same bytes, in the FP64 form
+  and with matrix-core passes and steps;
+* the matrix-core pass elementwise on both workloads.
 
 The oracle works on column chunks of X (FP64 copies of 1-2 GB), so its memory
 stays bounded; the chunk sums of the pass reorder FP64 additions only.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -20,6 +26,7 @@ import workloads
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 CHUNK = 50000
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def host_columns(Xt, storage, c0, c1):
@@ -161,3 +168,69 @@ def test_full_size_adaptive_bf16_exact_subspace(torch_cuda):
           (k, sin, rel, oracle.sin_theta(w["U"][:, :k], Ug)), flush=True)
     assert sin <= 1e-6
     assert rel <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def cfg2_oracle():
+    """The 2048 x 200000 FP32 workload from the NumPy generator and the stored
+    full oracle run on it (tests/golden, written by make_oracle_fixtures.py);
+    skipped when the fixture is absent or was made from other bytes."""
+    import sys
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    import make_oracle_fixtures as mk
+    name = "planted-2048x200000-f32"
+    path = mk.fixture_path(name, None)
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle run for %s" % name)
+    w = workloads.workload(name)
+    z = np.load(path)
+    if str(z["input_sha256"]) != mk.input_hash(w["Xt"]):
+        pytest.skip("stored oracle run was made from other input bytes")
+    return w, z
+
+
+@pytest.mark.parametrize("precision", [0, 4])
+def test_full_size_solve_against_oracle(torch_cuda, cfg2_oracle, precision):
+    """A whole solve of the 2048 x 200000 FP32 workload (FP64 form, and
+    matrix-core passes and steps) against the stored full oracle run: subspace
+    sine <= 1e-6, Ritz values, the relative Frobenius error to 1e-8 and the
+    (1 + eps) bound of Theorem "mainResult"."""
+    import torch
+    from paper_1607_02925_amd import lowrank
+    from oracle.linalg import sin_theta
+    w, z = cfg2_oracle
+    Uo, tho = z["U"], z["theta"]
+    Xt = torch.from_numpy(w["Xt"]).cuda()
+    plan = lowrank.Plan(Xt, w["k"], w["p"], w["eps"], seed=w["solver_seed"], precision=precision)
+    st, U, theta, rep = plan.solve()
+    Ug = U.cpu().numpy()
+    del plan, Xt
+    torch.cuda.empty_cache()
+    sin = sin_theta(Uo, Ug)
+    # ||X - U U^T X||_F^2 = ||X||_F^2 - ||U^T X||_F^2 (U orthonormal); X X^T for X_k
+    fro2, proj_g, proj_o = 0.0, 0.0, 0.0
+    G = np.zeros((w["d"], w["d"]))
+    for c0 in range(0, w["n"], CHUNK):
+        Xc = host_columns_np(w["Xt"], c0, min(w["n"], c0 + CHUNK))
+        fro2 += float(np.sum(Xc * Xc))
+        proj_g += float(np.sum((Ug.T @ Xc) ** 2))
+        proj_o += float(np.sum((Uo.T @ Xc) ** 2))
+        G += Xc @ Xc.T
+        del Xc
+    e_g, e_o = np.sqrt(fro2 - proj_g), np.sqrt(fro2 - proj_o)
+    lam = np.linalg.eigvalsh(G)[::-1]
+    e_k = np.sqrt(max(fro2 - float(np.sum(lam[:w["k"]])), 0.0))
+    print("full-size solve (precision %d): status %d outer %d/%d epochs %d/%d sin %.2e "
+          "||X - PX||_F gpu %.10e oracle %.10e best %.10e" %
+          (precision, st, rep["outer"], int(z["outer"]), rep["total_epochs"],
+           int(np.sum(z["epochs"])), sin, e_g, e_o, e_k), flush=True)
+    assert st == 0
+    assert sin <= 1e-6
+    np.testing.assert_allclose(theta, tho, rtol=1e-9)
+    assert abs(e_g - e_o) <= 1e-8 * e_o
+    assert e_g <= (1 + w["eps"]) * e_k
+
+
+def host_columns_np(xt, c0, c1):
+    """Columns c0..c1 of the NumPy-stored X (n x d rows) as a d x (c1 - c0) FP64 block."""
+    return np.ascontiguousarray(xt[c0:c1].astype(np.float64).T)

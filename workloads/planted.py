@@ -83,16 +83,25 @@ def _store(xt, storage):
     raise ValueError(storage)
 
 
+# BLAS threads of the generator: the QR factorisations and the product that
+# build X are blocked by thread count, so their rounding (and the stored bytes)
+# depends on it; a fixed count makes X the same on every host with at least
+# this many cores
+GEN_BLAS_THREADS = 8
+
+
 def planted_dense(d, n, sigma, seed, storage="f64", noise_std=0.0):
     """CPU (NumPy PCG64) generator.  Returns dict with Xt (n x d, storage
     type), U (d x d, planted left singular vectors), sigma (d,)."""
+    from threadpoolctl import threadpool_limits
     sigma = np.asarray(sigma, dtype=np.float64)
     assert sigma.shape == (min(d, n),)
     rng = np.random.default_rng(seed)
-    u = haar_orthogonal(d, rng)
     r = min(d, n)
-    v = _orthonormal_columns(n, r, rng)
-    xt = (v * sigma[None, :]) @ u[:, :r].T
+    with threadpool_limits(limits=GEN_BLAS_THREADS, user_api="blas"):
+        u = haar_orthogonal(d, rng)
+        v = _orthonormal_columns(n, r, rng)
+        xt = (v * sigma[None, :]) @ u[:, :r].T
     if noise_std:
         xt += noise_std * rng.standard_normal((n, d))
     return {"Xt": _store(xt, storage), "U": u, "sigma": sigma, "storage": storage,
