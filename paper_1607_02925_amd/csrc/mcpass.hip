@@ -127,6 +127,29 @@ __device__ __forceinline__ void load8(const TX* __restrict__ col, int64_t r, int
   }
 }
 
+// One 16-byte chunk (4 FP32 or 8 BF16 values) of a column from row r, as
+// load8 does it: VEC (d % 8 == 0) moves a chunk past d back to the last whole
+// chunk, the scalar form clamps each row to d - 1.
+template <typename TX, bool VEC>
+__device__ __forceinline__ u32x4 load_chunk(const TX* __restrict__ col, int64_t r, int64_t d) {
+  constexpr int E = 16 / (int)sizeof(TX);
+  if constexpr (VEC) {
+    return __builtin_nontemporal_load(
+        reinterpret_cast<const u32x4*>(col + (r + E <= d ? r : d - E)));
+  } else if constexpr (sizeof(TX) == 2) {
+    uint32_t w[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+      w[h] = (uint32_t)col[imin(r + 2 * h, d - 1)] | ((uint32_t)col[imin(r + 2 * h + 1, d - 1)] << 16);
+    return u32x4{w[0], w[1], w[2], w[3]};
+  } else {
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = __float_as_uint(col[imin(r + i, d - 1)]);
+    return u32x4{w[0], w[1], w[2], w[3]};
+  }
+}
+
 // W (d x p FP64, column-major) -> three BF16 parts in the B-operand order over
 // rows (k = row), zero past d and p.
 __global__ __launch_bounds__(256) void k_mc_split_w(const double* __restrict__ W, int64_t d,
@@ -147,12 +170,15 @@ __global__ __launch_bounds__(256) void k_mc_split_w(const double* __restrict__ W
   out[2 * wstride + o] = l;
 }
 
-// T = X^T W.  A workgroup takes one group of 128 columns; wave w owns columns
-// 16 w .. 16 w + 15 and runs over all 32-row blocks.  X is fetched PD blocks
-// ahead in registers; the W part tiles of the next block are staged in the
-// other LDS buffer, one barrier per block.  The main loop's steps are
-// unconditional and it stores nothing to memory, so each step waits only for
-// the loads of its own block.
+// T = X^T W for 64 columns per workgroup, all rows, in stages of 32 KPS rows.
+// A stage's 64 x 32 KPS tile of X is fetched column by column (the threads of
+// one column read its rows as one contiguous run of 256 or 512 bytes), kept in
+// registers two stages ahead and written to the other LDS buffer; the W part
+// tiles of the stage's row blocks travel the same way.  Wave w multiplies
+// column tile w % 4 over half the stage's row blocks (lane 16 q + c reads
+// rows 8 q .. 8 q + 7 of column c of a 32-row block from LDS as the A
+// operand); the two halves are added in a fixed order at the end.  One
+// barrier per stage; every load reads an in-bounds address outside any branch.
 template <typename TX, int NTW, bool VEC>
 __global__ __launch_bounds__(NW * 64) void k_mc_xtw(const TX* __restrict__ X, int64_t ld,
                                                     int64_t d, int64_t n,
@@ -161,23 +187,59 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xtw(const TX* __restrict__ X, in
                                                     int64_t tstride, int64_t tcols) {
   using XT = XTraits<TX>;
   constexpr int NPX = XT::NPX, NV = XT::NV;
-  constexpr int PD = 3, NSTG = PD + 1;           // blocks in flight, register stages
-  constexpr int TILES = NPART * NTW;             // W part tiles per row block
-  constexpr int WPT = (TILES * 64 + NW * 64 - 1) / (NW * 64);   // 16-byte words per thread
-  __shared__ u32x4 wsh[2][WPT * NW * 64];   // words past TILES * 64 are never read
+  constexpr int CB = 64;                                 // columns per workgroup
+  constexpr int KPS = NTW == 4 ? 2 : 4;                  // 32-row blocks per stage
+  constexpr int RS = 32 * KPS;                           // rows per stage
+  constexpr int EPC = 16 / (int)sizeof(TX);              // elements per 16-byte chunk
+  constexpr int CPC = RS / EPC;                          // chunks per column per stage
+  constexpr int XW = CB * CPC / (NW * 64);               // X chunks per thread per stage
+  constexpr int LDX = RS + EPC;                          // LDS column pitch (elements)
+  constexpr int TILES = KPS * NPART * NTW;               // W part tiles per stage
+  constexpr int WW = (TILES * 64 + NW * 64 - 1) / (NW * 64);
+  static_assert(CB * CPC % (NW * 64) == 0, "whole chunks per thread");
+  __shared__ __align__(16) TX xs[2][CB * LDX];
+  __shared__ u32x4 wsh[2][WW * NW * 64];                 // words past TILES * 64 are never read
+  static_assert(sizeof(double) * 4 * NTW * 4 * 64 <= sizeof(u32x4) * 2 * WW * NW * 64,
+                "the combine buffer fits in the W staging buffers");
+  // after the last stage the W staging buffers hold the second halves' sums
+  double (*comb)[NTW][4][64] = reinterpret_cast<double (*)[NTW][4][64]>(&wsh[0][0]);
   const int t = threadIdx.x, wave = t / 64, l = t % 64, li = l % 16, q = l / 16;
   const int NS = NTW;
-  const int64_t g0 = blockIdx.x;
-  const int64_t nkb = (d + 31) / 32, total = nkb;
-  auto w_word = [&](int64_t kb, int e) -> u32x4 {
-    e = e < TILES * 64 ? e : TILES * 64 - 1;
-    const int tile = e / 64, g = tile / NTW, u = tile % NTW;
-    return *reinterpret_cast<const u32x4*>(Wp + g * wstride + ((kb * NS + u) * 64 + e % 64) * 8);
+  const int mt = wave & 3, kh = wave >> 2;               // column tile, half of the row blocks
+  const int64_t c0 = (int64_t)blockIdx.x * CB;
+  const int64_t nst = (d + RS - 1) / RS;
+  struct Stage {
+    u32x4 x[XW];
+    u32x4 w[WW];
   };
-  // X chunk of row block i; blocks past the end re-read the last one
-  const TX* __restrict__ xcol = X + imin(g0 * 128 + 16 * wave + li, n - 1) * ld;
-  auto load_x = [&](u32x4 (&xs)[NV], int64_t i) {
-    load8<TX, VEC>(xcol, imin(i, total - 1) * 32 + 8 * q, d, xs);
+  auto load = [&](Stage& S, int64_t st) {
+    st = imin(st, nst - 1);
+#pragma unroll
+    for (int j = 0; j < XW; ++j) {
+      const int e = t + j * NW * 64, cc = e / CPC, ch = e % CPC;
+      const TX* __restrict__ col = X + imin(c0 + cc, n - 1) * ld;
+      const int64_t r = st * RS + (int64_t)ch * EPC;
+      S.x[j] = load_chunk<TX, VEC>(col, r, d);
+    }
+#pragma unroll
+    for (int j = 0; j < WW; ++j) {
+      int e = t + j * NW * 64;
+      e = e < TILES * 64 ? e : TILES * 64 - 1;
+      const int tile = e / 64, kb = tile / (NPART * NTW), g = (tile / NTW) % NPART, u = tile % NTW;
+      // the W parts hold zero rows up to a multiple of 128, so a stage past d
+      // meets zeros
+      const int64_t kbg = st * KPS + kb;
+      S.w[j] = *reinterpret_cast<const u32x4*>(Wp + g * wstride + ((kbg * NS + u) * 64 + e % 64) * 8);
+    }
+  };
+  auto stage_lds = [&](const Stage& S, int buf) {
+#pragma unroll
+    for (int j = 0; j < XW; ++j) {
+      const int e = t + j * NW * 64, cc = e / CPC, ch = e % CPC;
+      *reinterpret_cast<u32x4*>(&xs[buf][cc * LDX + ch * EPC]) = S.x[j];
+    }
+#pragma unroll
+    for (int j = 0; j < WW; ++j) wsh[buf][t + j * NW * 64] = S.w[j];
   };
   f32x4 acc[NTW];
   double accd[NTW][4];
@@ -187,19 +249,7 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xtw(const TX* __restrict__ X, in
 #pragma unroll
     for (int v = 0; v < 4; ++v) accd[u][v] = 0.0;
   }
-  auto compute = [&](const u32x4 (&xs)[NV], const u32x4* __restrict__ wb) {
-    bf16x8 xp[NPX];
-    a_parts<TX>(xs, xp);
-#pragma unroll
-    for (int g = 0; g < NPART; ++g)
-#pragma unroll
-      for (int u = 0; u < NTW; ++u) {
-        const bf16x8 wf = __builtin_bit_cast(bf16x8, wb[(g * NTW + u) * 64 + l]);
-#pragma unroll
-        for (int h = 0; h < NPX; ++h)
-          if (h + g < NPART) acc[u] = mfma(xp[h], wf, acc[u]);
-      }
-  };
+  int since = 0;   // row blocks accumulated in FP32 since the last flush
   auto flush = [&]() {
 #pragma unroll
     for (int u = 0; u < NTW; ++u) {
@@ -208,71 +258,98 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xtw(const TX* __restrict__ X, in
       acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
   };
-  // lane 16 q + c holds T[16 w + 4 q + v][16 u + c] of the group; lanes with
-  // even q take their partner's four rows and store eight consecutive columns
-  // of T (one 16-byte word per part), zero past n
-  __bf16* tout = reinterpret_cast<__bf16*>(Tp);
-  auto store_t = [&](int64_t g) {
+  auto compute = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < NTW; ++u) {
-      double v8[8];
+    for (int k = 0; k < KPS / 2; ++k) {
+      const int kb = kh * (KPS / 2) + k;
+      const TX* xa = &xs[buf][(mt * 16 + li) * LDX + kb * 32 + 8 * q];
+      u32x4 av[NV];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        v8[v] = accd[u][v];
-        v8[4 + v] = __shfl_down(accd[u][v], 16);
-        accd[u][v] = 0.0;
-      }
-      const int64_t ca = g * 128 + 16 * wave + 4 * q;
-      if ((q & 1) == 0 && ca < tcols) {
-        bf16x8 o[NPART];
+      for (int i = 0; i < NV; ++i) av[i] = reinterpret_cast<const u32x4*>(xa)[i];
+      bf16x8 xp[NPX];
+      a_parts<TX>(av, xp);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          __bf16 h, md, lo;
-          split3(ca + i < n ? v8[i] : 0.0, h, md, lo);
-          o[0][i] = h;
-          o[1][i] = md;
-          o[2][i] = lo;
+      for (int g = 0; g < NPART; ++g)
+#pragma unroll
+        for (int u = 0; u < NTW; ++u) {
+          const bf16x8 wf =
+              __builtin_bit_cast(bf16x8, wsh[buf][((kb * NPART + g) * NTW + u) * 64 + l]);
+#pragma unroll
+          for (int h = 0; h < NPX; ++h)
+            if (h + g < NPART) acc[u] = mfma(xp[h], wf, acc[u]);
         }
-        const int64_t off = bt_off(ca, 16 * u + li, NS);
-#pragma unroll
-        for (int g2 = 0; g2 < NPART; ++g2)
-          *reinterpret_cast<bf16x8*>(tout + g2 * tstride + off) = o[g2];
-      }
     }
   };
-  // W words of block i + 2 are fetched at step i into wr[i & 1] and staged in
-  // LDS at step i + 1, so their latency is hidden behind a whole step as well
-  u32x4 xs[NSTG][NV];
-  u32x4 wr[2][WPT];
-  auto step = [&](int64_t i, u32x4 (&cur)[NV], u32x4 (&ahead)[NV], u32x4 (&wload)[WPT],
-                  const u32x4 (&wstore)[WPT]) {
-#pragma unroll
-    for (int j = 0; j < WPT; ++j) wload[j] = w_word(imin(i + 2, nkb - 1), t + j * NW * 64);
-    load_x(ahead, i + PD);
-    compute(cur, wsh[i & 1]);
-    if ((i + 1) % FLUSH == 0) flush();
-#pragma unroll
-    for (int j = 0; j < WPT; ++j) wsh[(i + 1) & 1][t + j * NW * 64] = wstore[j];
+  // stage st + 1 goes to LDS (its loads were issued two stages earlier) and its
+  // registers are refilled with stage st + 3 while stage st is multiplied
+  auto step = [&](int64_t st, Stage& nxt) {
+    stage_lds(nxt, (int)((st + 1) & 1));
+    load(nxt, st + 3);
+    compute((int)(st & 1));
+    since += KPS / 2;
+    if (since >= FLUSH) {
+      flush();
+      since = 0;
+    }
     __syncthreads();
   };
-  for (int e = t; e < TILES * 64; e += NW * 64) wsh[0][e] = w_word(0, e);
-#pragma unroll
-  for (int j = 0; j < WPT; ++j) wr[1][j] = w_word(imin(1, nkb - 1), t + j * NW * 64);
-#pragma unroll
-  for (int j = 0; j < PD; ++j) load_x(xs[j], j);
-  __syncthreads();
-  int64_t i = 0;
-  for (; i + NSTG <= total; i += NSTG) {
-    step(i, xs[0], xs[3], wr[0], wr[1]);
-    step(i + 1, xs[1], xs[0], wr[1], wr[0]);
-    step(i + 2, xs[2], xs[1], wr[0], wr[1]);
-    step(i + 3, xs[3], xs[2], wr[1], wr[0]);
+  {
+    Stage A, B;
+    load(A, 0);
+    load(B, 1);
+    stage_lds(A, 0);
+    load(A, 2);
+    __syncthreads();
+    int64_t st = 0;
+    for (; st + 2 <= nst; st += 2) {
+      step(st, B);
+      step(st + 1, A);
+    }
+    if (st < nst) step(st, B);
   }
-  if (i < total) step(i, xs[0], xs[3], wr[0], wr[1]);
-  if (i + 1 < total) step(i + 1, xs[1], xs[0], wr[1], wr[0]);
-  if (i + 2 < total) step(i + 2, xs[2], xs[1], wr[0], wr[1]);
   flush();
-  store_t(g0);
+  // the second half of each column tile's row blocks is added to the first in
+  // a fixed order; waves 0..3 then hold T[c0 + 16 mt + 4 q + v][16 u + c]
+  if (kh == 1) {
+#pragma unroll
+    for (int u = 0; u < NTW; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) comb[mt][u][v][l] = accd[u][v];
+  }
+  __syncthreads();
+  if (kh == 1) return;
+#pragma unroll
+  for (int u = 0; u < NTW; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) accd[u][v] += comb[mt][u][v][l];
+  // lanes with even q take their partner's four rows and store eight
+  // consecutive columns of T (one 16-byte word per part), zero past n
+  __bf16* tout = reinterpret_cast<__bf16*>(Tp);
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) {
+    double v8[8];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      v8[v] = accd[u][v];
+      v8[4 + v] = __shfl_down(accd[u][v], 16);
+    }
+    const int64_t ca = c0 + 16 * mt + 4 * q;
+    if ((q & 1) == 0 && ca < tcols) {
+      bf16x8 o[NPART];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        __bf16 h, md, lo;
+        split3(ca + i < n ? v8[i] : 0.0, h, md, lo);
+        o[0][i] = h;
+        o[1][i] = md;
+        o[2][i] = lo;
+      }
+      const int64_t off = bt_off(ca, 16 * u + li, NS);
+#pragma unroll
+      for (int g2 = 0; g2 < NPART; ++g2)
+        *reinterpret_cast<bf16x8*>(tout + g2 * tstride + off) = o[g2];
+    }
+  }
 }
 
 // Partial sums of X T over the columns of split s for rows r0 .. r0 + 127;
@@ -457,7 +534,7 @@ McSizes mc_sizes(int64_t d, int64_t n, int PC) {
   const Split sp = mc_split(d, n);
   McSizes z;
   z.nsplit = sp.nsplit;
-  z.wp_elems = (int64_t)NPART * round_up(d, 32) * PC;
+  z.wp_elems = (int64_t)NPART * round_up(d, 128) * PC;   // zero rows up to a stage multiple
   z.tp_elems = (int64_t)NPART * round_up(n, 32) * PC;
   z.part_elems = (int64_t)sp.nsplit * sp.nrb * RB * PC;
   return z;
@@ -492,16 +569,16 @@ hipError_t mc_pass(const XView& X, const double* W, int p, int PC, const McBufs&
       p < 1 || p > PC || X.d < 1 || X.n < 1)
     return hipErrorInvalidValue;
   const Split sp = mc_split(X.d, X.n);
-  const int64_t wstride = round_up(X.d, 32) * PC, tstride = round_up(X.n, 32) * PC;
+  const int64_t wstride = round_up(X.d, 128) * PC, tstride = round_up(X.n, 32) * PC;
   if (sp.nsplit != mb.nsplit || wstride != mb.wstride || tstride != mb.tstride)
     return hipErrorInvalidValue;
   const int64_t pstride = (int64_t)sp.nrb * RB * PC;
-  const int64_t wrows = round_up(X.d, 32);
+  const int64_t wrows = round_up(X.d, 128);
   k_mc_split_w<<<(unsigned)((wrows * PC + 255) / 256), 256, 0, st>>>(W, X.d, p, PC, wrows, mb.Wp,
                                                                      wstride);
   const int64_t tcols = round_up(X.n, 32);
   const bool vec = X.d % 8 == 0 && X.d >= 8;
-  const dim3 g1((unsigned)((X.n + 127) / 128));
+  const dim3 g1((unsigned)((X.n + 63) / 64));
   const dim3 g2((unsigned)(sp.nrb * sp.nsplit));
 #define MC_LAUNCH(TX, NTW, VEC)                                                              \
   do {                                                                                       \
