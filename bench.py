@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="solve",
-                    choices=["solve", "pass", "epoch", "copy", "serve", "sparse", "steps"])
+                    choices=["solve", "pass", "epoch", "copy", "serve", "sparse", "sparse-solve",
+                             "steps"])
     ap.add_argument("--sparse-workload", default=SPARSE_WORKLOAD)
     ap.add_argument("--sparse-steps", type=int, default=200,
                     help="sparse/steps: inner steps timed (one epoch of this length)")
@@ -287,6 +288,30 @@ def sparse_bench(args, dev):
     return out
 
 
+def sparse_solve(args, dev):
+    """One whole solve (q = k branch, FP64) of the compressed-column workload;
+    a few minutes, so not part of the default run."""
+    import torch
+    import workloads
+    from paper_1607_02925_amd import lowrank
+    w = workloads.workload(args.sparse_workload)
+    X = lowrank.CscMatrix.from_arrays(w["d"], w["n"], w["col_ptr"], w["row_idx"], w["values"],
+                                      device=dev)
+    log("generated %s" % args.sparse_workload)
+    plan = lowrank.Plan(X, w["k"], w["p"], w["eps"], seed=w["solver_seed"], timing=1)
+    torch.cuda.synchronize()
+    t = time.time()
+    st, U, theta, rep = plan.solve()
+    torch.cuda.synchronize()
+    sc = plan.schedule()
+    return {"workload": args.sparse_workload, "status": st, "seconds": time.time() - t,
+            "outer": rep["outer"], "epochs": rep["total_epochs"], "passes": rep["passes"],
+            "inner_steps": rep["steps"], "shift_rounds": rep["shift_rounds"], "lambda": sc.lam,
+            "b": sc.b, "m": sc.m, "theta": [float(x) for x in theta],
+            "ms_pass": rep["ms_pass_total"] / max(rep["timed_passes"], 1),
+            "us_step": rep["ms_steps_total"] * 1e3 / max(rep["timed_steps"], 1)}
+
+
 def steps_bench(args, dev):
     """Dense workload: one pass and one epoch of --sparse-steps inner steps at
     minibatch b (default 4096) in the chosen precision, with a shift 5% above
@@ -510,6 +535,10 @@ def main():
     if args.mode == "sparse":
         out = sparse_bench(args, dev)
         print(json.dumps({"mode": "sparse", **out}), flush=True)
+        return
+    if args.mode == "sparse-solve":
+        out = sparse_solve(args, dev)
+        print(json.dumps({"mode": "sparse-solve", **out}), flush=True)
         return
     if args.mode == "steps":
         out = steps_bench(args, dev)
