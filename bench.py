@@ -485,6 +485,15 @@ def serve_bench(args, dev):
                 out["batched_closed_matrix_core"]["max_sin_vs_fp64_steps"].items())
         log("serve batched closed loop, matrix-core steps: %s" %
             json.dumps(out["batched_closed_matrix_core"]))
+        # the same form against the arrival process: served as requests arrive
+        out["batched_open_matrix_core"], mco_outs = serve_run(reqs, Xown, args.slots, budget,
+                                                              open_loop=True, matrix_core=True)
+        # every result is bitwise the same whichever requests shared the device with it
+        same_mc = [torch.equal(a[1], b[1]) for a, b in zip(mc_outs, mco_outs)]
+        out["matrix_core_closed_equals_open"] = "%d/%d" % (sum(same_mc), len(same_mc))
+        out["matrix_core_mix_invariant"] = all(same_mc)
+        log("serve batched open loop, matrix-core: %s" %
+            json.dumps(out["batched_open_matrix_core"]))
     if seq_outs is not None and closed_outs is not None:
         same = [torch.equal(a[1], b[1]) for r, a, b in zip(reqs, seq_outs, closed_outs)
                 if r["storage"] == "f32"]
@@ -497,10 +506,11 @@ def serve_bench(args, dev):
                 out["batched_closed_matrix_core"]["solves_per_s"] / \
                 out["fp32_per_request"]["solves_per_s"]
     failed = [name for name in ("fp32_per_request", "batched_closed", "batched_open",
-                                "batched_closed_matrix_core")
+                                "batched_closed_matrix_core", "batched_open_matrix_core")
               if name in out and out[name]["failed"]]
     out["consistent"] = (not failed and out.get("alone_equals_mix", True) and
-                         out.get("matrix_core_agrees", True))
+                         out.get("matrix_core_agrees", True) and
+                         out.get("matrix_core_mix_invariant", True))
     return out
 
 

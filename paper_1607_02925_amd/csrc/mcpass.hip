@@ -368,8 +368,11 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xt(const TX* __restrict__ X, int
   constexpr int NPX = XT::NPX, NV = XT::NV;
   constexpr int TT = NPART * NTW;                      // T part tiles per column block
   constexpr int TPT = (TT * 64 + NW * 64 - 1) / (NW * 64);
-  constexpr int LDP = sizeof(TX) == 4 ? 33 : 34;       // LDS row pitch (elements)
-  __shared__ TX xs[2][RB * LDP];
+  // X tile in LDS column by column, pitch CP elements: a thread's 8 rows of one
+  // column go in as 8-byte stores, and the 64 lanes reading column 8 q + i of
+  // rows 16 w + c meet 64 distinct banks (CP = 130 words; BF16: 66 words)
+  constexpr int CP = sizeof(TX) == 4 ? 130 : 132;
+  __shared__ __align__(16) TX xs[2][32 * CP];
   __shared__ u32x4 ts[2][TPT * NW * 64];   // words past TT * 64 are never read
   const int t = threadIdx.x, wave = t / 64, l = t % 64, li = l % 16, q = l / 16;
   const int NS = NTW;
@@ -398,12 +401,15 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xt(const TX* __restrict__ X, int
     }
   };
   auto stage_lds = [&](const Stage& S, int buf) {
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&xs[buf][cc * CP + rr]);
+    if constexpr (sizeof(TX) == 4) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      if constexpr (sizeof(TX) == 4)
-        xs[buf][(rr + i) * LDP + cc] = __uint_as_float(S.x[i / 4][i % 4]);
-      else
-        xs[buf][(rr + i) * LDP + cc] = (uint16_t)(S.x[0][i / 2] >> (16 * (i % 2)));
+      for (int i = 0; i < 4; ++i)
+        reinterpret_cast<uint2*>(dst)[i] = make_uint2(S.x[i / 2][2 * (i % 2)], S.x[i / 2][2 * (i % 2) + 1]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        reinterpret_cast<uint2*>(dst)[i] = make_uint2(S.x[0][2 * i], S.x[0][2 * i + 1]);
     }
 #pragma unroll
     for (int i = 0; i < TPT; ++i) ts[buf][t + i * NW * 64] = S.tw[i];
@@ -416,16 +422,21 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xt(const TX* __restrict__ X, int
 #pragma unroll
     for (int v = 0; v < 4; ++v) accd[u][v] = 0.0;
   }
-  const int arow = (wave * 16 + li) * LDP + 8 * q;
+  const int arow = 8 * q * CP + wave * 16 + li;   // column 8 q of the block, row 16 w + c
   auto compute = [&](int buf) {
     u32x4 av[NV];
     if constexpr (sizeof(TX) == 4) {
       const uint32_t* xw = reinterpret_cast<const uint32_t*>(xs[buf]) + arow;
-      av[0] = u32x4{xw[0], xw[1], xw[2], xw[3]};
-      av[1] = u32x4{xw[4], xw[5], xw[6], xw[7]};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        av[0][i] = xw[i * CP];
+        av[1][i] = xw[(4 + i) * CP];
+      }
     } else {
-      const uint32_t* xw = reinterpret_cast<const uint32_t*>(xs[buf]) + arow / 2;
-      av[0] = u32x4{xw[0], xw[1], xw[2], xw[3]};
+      const uint16_t* xh = reinterpret_cast<const uint16_t*>(xs[buf]) + arow;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        av[0][i] = (uint32_t)xh[2 * i * CP] | ((uint32_t)xh[(2 * i + 1) * CP] << 16);
     }
     bf16x8 xp[NPX];
     a_parts<TX>(av, xp);

@@ -136,3 +136,33 @@ def test_mc_powerlaw_prefix_replay(torch_cuda):
     assert st == 0
     assert sin <= 1e-3
     np.testing.assert_allclose(theta, tho, rtol=1e-5)
+
+
+def test_mc_served_bitwise_alone(torch_cuda):
+    """Matrix-core-form requests (LR_PREC_MC) of mixed shapes and storage types
+    are bitwise the same solved alone and served concurrently in a mix: the
+    pass kernels reduce in a fixed order and each request has its own
+    workspace."""
+    from paper_1607_02925_amd import lowrank
+    torch = torch_cuda
+    shapes = [(256, 6000, 3, "f32"), (512, 5000, 6, "bf16"), (192, 7000, 2, "f32"),
+              (384, 4500, 5, "bf16"), (1024, 9000, 8, "f32"), (136, 4100, 4, "bf16")]
+    xs = [to_dev(torch, planted(d, n, k, 900 + d, st), st) for d, n, k, st in shapes]
+    ks = [k for _, _, k, _ in shapes]
+    alone = []
+    for X, k in zip(xs, ks):
+        st, U, th, rep = lowrank.Plan(X, k, k + 8, 1e-4, seed=5,
+                                      precision=lowrank.LR_PREC_MC).solve()
+        assert st == 0 and rep["mc_passes"] > 0
+        alone.append((st, U.clone(), th))
+    srv = lowrank.Server(1 << 30, slots=4)
+    tickets = [srv.submit(X, k, k + 8, 1e-4, seed=5, precision=lowrank.LR_PREC_MC)
+               for X, k in zip(xs, ks)]
+    outs = [srv.wait(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    assert stats["peak_running"] >= 2
+    for a, o in zip(alone, outs):
+        assert a[0] == o[0] == 0
+        assert torch.equal(a[1], o[1])
+        assert np.array_equal(a[2], o[2])
