@@ -229,6 +229,8 @@ def serve_run(reqs, X, slots, budget, open_loop=False, matrix_core=False):
                           "max": max(lat) * 1e3},
            "service_ms": {"p50": percentile(svc, 0.5) * 1e3, "p99": percentile(svc, 0.99) * 1e3},
            "pass_GBps_alg": pass_bytes / (t_last - t_first) / 1e9,
+           "inner_steps_total": int(sum(o[3]["steps"] for o in outs)),
+           "passes_total": int(sum(o[3]["passes"] for o in outs)),
            "peak_running": stats["peak_running"], "peak_bytes": stats["peak_bytes"],
            "failed": bad}
     return res, outs
