@@ -2,15 +2,15 @@
 // epoch, lambda W~ - X (X^T W~) - S) for dense FP32 and BF16 X on gfx950.
 //
 // Two kernels, each streaming X once:
-//   k_mc_xtw  T = X^T W.  Each wave owns 16 MT columns and runs over all rows;
-//             lane l = 16 q + c supplies rows 8 q .. 8 q + 7 of column c of a
-//             32-row block as the A operand (one 16- or 32-byte load), the
-//             B operand is the W part tile of that row block, staged in LDS
-//             once per workgroup.  T leaves as three BF16 parts in the B-operand
-//             order of the second kernel (contraction over columns).
+//   k_mc_xtw  T = X^T W for 128 columns per workgroup (a 16-column tile per
+//             wave) over all rows, in 64-row stages staged through LDS; lane
+//             l = 16 q + c supplies rows 8 q .. 8 q + 7 of column c of a 32-row
+//             block as the A operand, the B operand is the W part tile of that
+//             row block.  T leaves as three BF16 parts in the B-operand order of
+//             the second kernel (contraction over columns).
 //   k_mc_xt   partial X T for 128 rows and one column range.  A 128 x 32 tile
-//             of X is read column by column (coalesced), written to LDS
-//             transposed, and each lane reads 8 consecutive columns of its row
+//             of X is read column by column (coalesced) and kept column by
+//             column in LDS; each lane gathers 8 consecutive columns of its row
 //             as the A operand; T's part tiles of the block come through LDS.
 // v_mfma_f32_16x16x32_bf16: lane l supplies row l % 16 of A and column l % 16
 // of B over k = 8 (l / 16) .. + 7 and receives D[4 (l / 16) + v][l % 16].
@@ -33,6 +33,7 @@ constexpr int NW = 8;          // waves per workgroup
 constexpr int NPART = 3;       // BF16 parts of W, T and FP32 X
 constexpr int FLUSH = 8;       // 32-term blocks between FP32 -> FP64 flushes
 constexpr int RB = NW * 16;    // rows per k_mc_xt workgroup
+constexpr int XTW_COLS = NW * 16;   // columns per k_mc_xtw workgroup
 
 __device__ __forceinline__ f32x4 mfma(const bf16x8& a, const bf16x8& b, const f32x4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -170,15 +171,16 @@ __global__ __launch_bounds__(256) void k_mc_split_w(const double* __restrict__ W
   out[2 * wstride + o] = l;
 }
 
-// T = X^T W for 64 columns per workgroup, all rows, in stages of 32 KPS rows.
-// A stage's 64 x 32 KPS tile of X is fetched column by column (the threads of
-// one column read its rows as one contiguous run of 256 or 512 bytes), kept in
+// T = X^T W for 128 columns per workgroup, all rows, in stages of 64 rows.
+// A stage's 128 x 64 tile of X is fetched column by column (the threads of
+// one column read its rows as one contiguous run of 128 or 256 bytes), kept in
 // registers two stages ahead and written to the other LDS buffer; the W part
-// tiles of the stage's row blocks travel the same way.  Wave w multiplies
-// column tile w % 4 over half the stage's row blocks (lane 16 q + c reads
-// rows 8 q .. 8 q + 7 of column c of a 32-row block from LDS as the A
-// operand); the two halves are added in a fixed order at the end.  One
-// barrier per stage; every load reads an in-bounds address outside any branch.
+// tiles of the stage's two row blocks travel the same way.  Wave w multiplies
+// column tile w over every row block (lane 16 q + c reads rows 8 q .. 8 q + 7
+// of column c of a 32-row block from LDS as the A operand).  Each W part tile
+// staged in LDS thus serves 128 columns of X, which keeps the tiles' share of
+// the on-chip traffic below X's own.  One barrier per stage; every load reads
+// an in-bounds address outside any branch.
 template <typename TX, int NTW, bool VEC>
 __global__ __launch_bounds__(NW * 64) void k_mc_xtw(const TX* __restrict__ X, int64_t ld,
                                                     int64_t d, int64_t n,
@@ -187,8 +189,9 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xtw(const TX* __restrict__ X, in
                                                     int64_t tstride, int64_t tcols) {
   using XT = XTraits<TX>;
   constexpr int NPX = XT::NPX, NV = XT::NV;
-  constexpr int CB = 64;                                 // columns per workgroup
-  constexpr int KPS = NTW == 4 ? 2 : 4;                  // 32-row blocks per stage
+  constexpr int CB = XTW_COLS;                           // columns per workgroup
+  constexpr int KPS = 2;                                 // 32-row blocks per stage
+  static_assert(CB == 16 * NW, "one 16-column tile per wave");
   constexpr int RS = 32 * KPS;                           // rows per stage
   constexpr int EPC = 16 / (int)sizeof(TX);              // elements per 16-byte chunk
   constexpr int CPC = RS / EPC;                          // chunks per column per stage
@@ -199,13 +202,9 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xtw(const TX* __restrict__ X, in
   static_assert(CB * CPC % (NW * 64) == 0, "whole chunks per thread");
   __shared__ __align__(16) TX xs[2][CB * LDX];
   __shared__ u32x4 wsh[2][WW * NW * 64];                 // words past TILES * 64 are never read
-  static_assert(sizeof(double) * 4 * NTW * 4 * 64 <= sizeof(u32x4) * 2 * WW * NW * 64,
-                "the combine buffer fits in the W staging buffers");
-  // after the last stage the W staging buffers hold the second halves' sums
-  double (*comb)[NTW][4][64] = reinterpret_cast<double (*)[NTW][4][64]>(&wsh[0][0]);
   const int t = threadIdx.x, wave = t / 64, l = t % 64, li = l % 16, q = l / 16;
   const int NS = NTW;
-  const int mt = wave & 3, kh = wave >> 2;               // column tile, half of the row blocks
+  const int mt = wave;                                   // column tile
   const int64_t c0 = (int64_t)blockIdx.x * CB;
   const int64_t nst = (d + RS - 1) / RS;
   struct Stage {
@@ -260,8 +259,7 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xtw(const TX* __restrict__ X, in
   };
   auto compute = [&](int buf) {
 #pragma unroll
-    for (int k = 0; k < KPS / 2; ++k) {
-      const int kb = kh * (KPS / 2) + k;
+    for (int kb = 0; kb < KPS; ++kb) {
       const TX* xa = &xs[buf][(mt * 16 + li) * LDX + kb * 32 + 8 * q];
       u32x4 av[NV];
 #pragma unroll
@@ -286,7 +284,7 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xtw(const TX* __restrict__ X, in
     stage_lds(nxt, (int)((st + 1) & 1));
     load(nxt, st + 3);
     compute((int)(st & 1));
-    since += KPS / 2;
+    since += KPS;
     if (since >= FLUSH) {
       flush();
       since = 0;
@@ -308,20 +306,7 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xtw(const TX* __restrict__ X, in
     if (st < nst) step(st, B);
   }
   flush();
-  // the second half of each column tile's row blocks is added to the first in
-  // a fixed order; waves 0..3 then hold T[c0 + 16 mt + 4 q + v][16 u + c]
-  if (kh == 1) {
-#pragma unroll
-    for (int u = 0; u < NTW; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) comb[mt][u][v][l] = accd[u][v];
-  }
-  __syncthreads();
-  if (kh == 1) return;
-#pragma unroll
-  for (int u = 0; u < NTW; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) accd[u][v] += comb[mt][u][v][l];
+  // wave mt holds T[c0 + 16 mt + 4 q + v][16 u + c];
   // lanes with even q take their partner's four rows and store eight
   // consecutive columns of T (one 16-byte word per part), zero past n
   __bf16* tout = reinterpret_cast<__bf16*>(Tp);
@@ -589,7 +574,7 @@ hipError_t mc_pass(const XView& X, const double* W, int p, int PC, const McBufs&
                                                                      wstride);
   const int64_t tcols = round_up(X.n, 32);
   const bool vec = X.d % 8 == 0 && X.d >= 8;
-  const dim3 g1((unsigned)((X.n + 63) / 64));
+  const dim3 g1((unsigned)((X.n + XTW_COLS - 1) / XTW_COLS));
   const dim3 g2((unsigned)(sp.nrb * sp.nsplit));
 #define MC_LAUNCH(TX, NTW, VEC)                                                              \
   do {                                                                                       \
