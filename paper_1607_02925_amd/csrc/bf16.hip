@@ -92,6 +92,11 @@ __global__ __launch_bounds__(NW * 64) void k_sdot_bf16(
   const int64_t s0 = (int64_t)blockIdx.x * 16;
   const int64_t s = s0 + li;
   const uint16_t* __restrict__ xcol = X + (int64_t)idx[s < b ? s : 0] * ld;
+  // the epilogue's weight, loaded now so that its latency hides under the loop
+  // (thread t writes sample row i = (t / 16) % 16 of every slice)
+  static_assert((NW * 64) % 256 == 0, "a thread keeps its sample row across slices");
+  const int64_t sw = s0 + (t / 16) % 16;
+  const double wsc = scale[sw < b ? sw : 0];
   f32x4 ah[NTW], al[NTW];
 #pragma unroll
   for (int u = 0; u < NTW; ++u) ah[u] = al[u] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -160,7 +165,7 @@ __global__ __launch_bounds__(NW * 64) void k_sdot_bf16(
     const int64_t ss = s0 + i;
     if (ss < b) {
       const int64_t o = bt_off(ss, u * 16 + jj, NS);
-      split2(scale[ss] * sum, &Ch[o], &Cl[o]);
+      split2(wsc * sum, &Ch[o], &Cl[o]);
     }
   }
 }

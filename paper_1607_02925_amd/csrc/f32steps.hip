@@ -130,6 +130,10 @@ __global__ __launch_bounds__(NW * 64) void k_sdot_f32(const TX* __restrict__ X, 
   const int t = threadIdx.x, wave = t / 64, l = t % 64, c = l % 16, q = l / 16;
   const int64_t s0 = (int64_t)blockIdx.x * 16;
   const TX* __restrict__ xcol = X + (int64_t)idx[s0 + c < b ? s0 + c : 0] * ld;
+  // the epilogue's weight, loaded now so that its latency hides under the loop
+  // (thread t writes rows i = (t % 256) / 16 of every slice)
+  const int64_t sw = s0 + (t % 256) / 16;
+  const double wsc = scale[sw < b ? sw : 0];
   f32x4 acc[NT];
 #pragma unroll
   for (int v = 0; v < NT; ++v) acc[v] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -187,10 +191,11 @@ __global__ __launch_bounds__(NW * 64) void k_sdot_f32(const TX* __restrict__ X, 
   // rows from b up to the next multiple of 16 are written as zeros (the update
   // reads whole 16-sample blocks)
   float* __restrict__ out = C32 + (int64_t)blockIdx.z * cstride;
+  static_assert((NW * 64) % 256 == 0, "a thread keeps its row i across slices");
   for (int e = t; e < NT * 256; e += NW * 64) {
     const int v = e / 256, i = (e % 256) / 16, j = e % 16;
     const int64_t ss = s0 + i;
-    out[t32_off(ss, v * 16 + j, NT)] = ss < b ? (float)(scale[ss] * red[e]) : 0.f;
+    out[t32_off(ss, v * 16 + j, NT)] = ss < b ? (float)(wsc * red[e]) : 0.f;
   }
 }
 
@@ -221,6 +226,20 @@ __global__ __launch_bounds__(NW * 64) void k_supd_f32(const TX* __restrict__ X, 
   const int64_t r0 = tile * 16;
   if (r0 >= d) return;
   const int u0 = blockIdx.y * NT;
+  // thread t < NT * 256 updates element (r0 + (t % 256) / 16, column (u0 + t / 256) 16 + t % 16)
+  // in the epilogue; its FP64 operands are loaded now so that their latency
+  // hides under the loop (an element past d or p reads element 0 and is not stored)
+  static_assert(NW * 64 >= NT * 256, "one element per thread");
+  const int ei = (t % 256) / 16, ej = (u0 + t / 256) * 16 + t % 16;
+  const int64_t er = r0 + ei;
+  const bool eown = t < NT * 256 && er < d && ej < p;
+  int64_t eo = 0;
+  if (eown) {
+    const int rho = (int)(er & 15), qq = rho >> 2, ss = rho & 3;
+    eo = ((er >> 4) * NS + (ej >> 4)) * 256 + (ss >> 1) * 128 + (qq * 16 + (ej & 15)) * 2 + (ss & 1);
+  }
+  const double edl = Dl[eo];
+  const double egr = Gr[eown ? (int64_t)ej * d + er : 0];
   const int64_t bpad = (b + 15) / 16 * 16;
   for (int64_t e = t; e < bpad; e += NW * 64) sidx[e] = idx[e < b ? e : 0];
   __syncthreads();
@@ -281,19 +300,11 @@ __global__ __launch_bounds__(NW * 64) void k_supd_f32(const TX* __restrict__ X, 
     }
   }
   waves_sum32<NW, NT>(red, slots, acc, q, c);
-  for (int e = t; e < NT * 256; e += NW * 64) {
-    const int i = (e % 256) / 16, j = (u0 + e / 256) * 16 + e % 16;
-    const int64_t r = r0 + i;
-    if (r < d && j < p) {
-      // the FP64 master, tile-major as on the FP64 path
-      const int rho = (int)(r & 15), qq = rho >> 2, ss = rho & 3;
-      const int64_t o = ((r >> 4) * NS + (j >> 4)) * 256 + (ss >> 1) * 128 +
-                        (qq * 16 + (j & 15)) * 2 + (ss & 1);
-      const double x0 = Dl[o];
-      const double x = x0 - eta * (Gr[(int64_t)j * d + r] + lam * x0 - red[e]);
-      Dl[o] = x;
-      D32[t32_off(r, j, NS)] = (float)x;
-    }
+  if (eown) {
+    // the FP64 master, tile-major as on the FP64 path
+    const double x = edl - eta * (egr + lam * edl - red[t]);
+    Dl[eo] = x;
+    D32[t32_off(er, ej, NS)] = (float)x;
   }
 }
 
