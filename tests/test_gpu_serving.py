@@ -141,3 +141,39 @@ def test_server_errors_and_polling(data):
         srv.poll(tg)          # ticket already collected
     srv.close()
     torch.cuda.synchronize()
+
+
+def test_trace_mix_bitwise_alone():
+    """A 64-request slice of the serving trace (its d, n, k, p and storage mix,
+    with d capped at 1024 and n at 32768 to keep the test short), every other
+    request in the matrix-core form: each result is bitwise the same solved
+    alone and served by 8 slots with all 64 submitted at once, where at least
+    four run together."""
+    import torch
+    from paper_1607_02925_amd import lowrank
+    reqs = serving.trace(count=64, seed=11, d_choices=(256, 512, 1024), n_range=(4096, 32768))
+    xs = [serving.request_data(r, device="cuda") for r in reqs]   # FP32 or BF16 tensors
+    torch.cuda.synchronize()
+    prec = [lowrank.LR_PREC_MC if i % 2 else 0 for i in range(len(reqs))]
+    alone = []
+    for r, X, pr in zip(reqs, xs, prec):
+        plan = lowrank.Plan(X, r["k"], r["p"], r["eps"], seed=r["solver_seed"], precision=pr)
+        st, U, theta, rep = plan.solve()
+        plan.close()
+        alone.append((st, U.clone(), theta, rep["outer"]))
+    print("alone: %d solves, %d matrix-core" % (len(reqs), sum(1 for p_ in prec if p_)),
+          flush=True)
+    srv = lowrank.Server(1 << 31, slots=8)
+    tickets = [srv.submit(X, r["k"], r["p"], r["eps"], seed=r["solver_seed"], precision=pr)
+               for r, X, pr in zip(reqs, xs, prec)]
+    outs = [srv.wait(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    print("server stats:", stats, flush=True)
+    assert stats["peak_running"] >= 4
+    same = 0
+    for r, a, o in zip(reqs, alone, outs):
+        assert a[0] == o[0] == 0, (r, a[0], o[0])
+        same += int(torch.equal(a[1], o[1]) and np.array_equal(a[2], o[2]) and
+                    a[3] == o[3]["outer"])
+    assert same == len(reqs), "%d of %d bitwise equal" % (same, len(reqs))
