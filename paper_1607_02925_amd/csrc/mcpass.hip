@@ -8,7 +8,7 @@
 //             block as the A operand, the B operand is the W part tile of that
 //             row block.  T leaves as three BF16 parts in the B-operand order of
 //             the second kernel (contraction over columns).
-//   k_mc_xt   partial X T for 128 rows and one column range.  A 128 x 32 tile
+//   k_mc_xt   partial X T for 256 rows and one column range.  A 256 x 32 tile
 //             of X is read column by column (coalesced) and kept column by
 //             column in LDS; each lane gathers 8 consecutive columns of its row
 //             as the A operand; T's part tiles of the block come through LDS.
@@ -32,7 +32,8 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int NW = 8;          // waves per workgroup
 constexpr int NPART = 3;       // BF16 parts of W, T and FP32 X
 constexpr int FLUSH = 8;       // 32-term blocks between FP32 -> FP64 flushes
-constexpr int RB = NW * 16;    // rows per k_mc_xt workgroup
+constexpr int XT_MT = 2;             // 16-row tiles per wave in k_mc_xt
+constexpr int RB = NW * 16 * XT_MT;  // rows per k_mc_xt workgroup
 constexpr int XTW_COLS = NW * 16;   // columns per k_mc_xtw workgroup
 
 __device__ __forceinline__ f32x4 mfma(const bf16x8& a, const bf16x8& b, const f32x4& c) {
@@ -337,12 +338,14 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xtw(const TX* __restrict__ X, in
   }
 }
 
-// Partial sums of X T over the columns of split s for rows r0 .. r0 + 127;
+// Partial sums of X T over the columns of split s for rows r0 .. r0 + RB - 1;
 // workgroup -> (split, row block) keeps every row block of a split on one XCD
-// so the split's T tiles are fetched into one L2.  Each thread fetches one
-// column's 8-row chunk of the next-but-one 32-column block and its share of
-// the T part tiles; a block is staged (X transposed) in the other LDS buffer
-// while the current one is multiplied, one barrier per block.
+// so the split's T tiles are fetched into one L2, and a row block of 256 rows
+// (two 16-row tiles per wave) halves how often each T tile is fetched and read
+// from LDS against 128 rows.  Each thread fetches one column's 8-row chunks of
+// the next-but-one 32-column block and its share of the T part tiles; a block
+// is staged in the other LDS buffer while the current one is multiplied, one
+// barrier per block.
 // part: row-major rows x PC.
 template <typename TX, int NTW, bool VEC>
 __global__ __launch_bounds__(NW * 64) void k_mc_xt(const TX* __restrict__ X, int64_t ld, int64_t d,
@@ -355,8 +358,9 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xt(const TX* __restrict__ X, int
   constexpr int TPT = (TT * 64 + NW * 64 - 1) / (NW * 64);
   // X tile in LDS column by column, pitch CP elements: a thread's 8 rows of one
   // column go in as 8-byte stores, and the 64 lanes reading column 8 q + i of
-  // rows 16 w + c meet 64 distinct banks (CP = 130 words; BF16: 66 words)
-  constexpr int CP = sizeof(TX) == 4 ? 130 : 132;
+  // rows 16 t + c of tile t meet 64 distinct banks (CP = RB + 2 = 258 words, 2 mod 64;
+  // BF16: 130 words, also 2 mod 64, two lanes sharing each word)
+  constexpr int CP = sizeof(TX) == 4 ? RB + 2 : RB + 4;
   __shared__ __align__(16) TX xs[2][32 * CP];
   __shared__ u32x4 ts[2][TPT * NW * 64];   // words past TT * 64 are never read
   const int t = threadIdx.x, wave = t / 64, l = t % 64, li = l % 16, q = l / 16;
@@ -366,16 +370,17 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xt(const TX* __restrict__ X, int
   const int64_t r0 = (int64_t)(loc % nrb) * RB;
   const int64_t kb0 = s * kper / 32;
   const int64_t kb1 = imin((s + 1) * kper, (n + 31) / 32 * 32) / 32;
-  // loader: column cc of the block, rows rr .. rr + 7 of the row block
+  // loader: column cc of the block, rows rr + 128 h .. + 7 of the row block (h < XT_MT)
   const int cc = t / 16, rr = (t % 16) * 8;
   struct Stage {
-    u32x4 x[NV];
+    u32x4 x[XT_MT][NV];
     u32x4 tw[TPT];
   };
   auto load = [&](Stage& S, int64_t kb) {
     kb = imin(kb, kb1 - 1);
     const int64_t col = imin(kb * 32 + cc, n - 1);
-    load8<TX, VEC>(X + col * ld, r0 + rr, d, S.x);
+#pragma unroll
+    for (int h = 0; h < XT_MT; ++h) load8<TX, VEC>(X + col * ld, r0 + rr + 128 * h, d, S.x[h]);
 #pragma unroll
     for (int i = 0; i < TPT; ++i) {
       int e = t + i * NW * 64;
@@ -386,62 +391,78 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xt(const TX* __restrict__ X, int
     }
   };
   auto stage_lds = [&](const Stage& S, int buf) {
-    uint32_t* dst = reinterpret_cast<uint32_t*>(&xs[buf][cc * CP + rr]);
-    if constexpr (sizeof(TX) == 4) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        reinterpret_cast<uint2*>(dst)[i] = make_uint2(S.x[i / 2][2 * (i % 2)], S.x[i / 2][2 * (i % 2) + 1]);
-    } else {
+    for (int h = 0; h < XT_MT; ++h) {
+      uint32_t* dst = reinterpret_cast<uint32_t*>(&xs[buf][cc * CP + rr + 128 * h]);
+      if constexpr (sizeof(TX) == 4) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        reinterpret_cast<uint2*>(dst)[i] = make_uint2(S.x[0][2 * i], S.x[0][2 * i + 1]);
+        for (int i = 0; i < 4; ++i)
+          reinterpret_cast<uint2*>(dst)[i] =
+              make_uint2(S.x[h][i / 2][2 * (i % 2)], S.x[h][i / 2][2 * (i % 2) + 1]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          reinterpret_cast<uint2*>(dst)[i] = make_uint2(S.x[h][0][2 * i], S.x[h][0][2 * i + 1]);
+      }
     }
 #pragma unroll
     for (int i = 0; i < TPT; ++i) ts[buf][t + i * NW * 64] = S.tw[i];
   };
-  f32x4 acc[NTW];
-  double accd[NTW][4];
+  f32x4 acc[XT_MT][NTW];
+  double accd[XT_MT][NTW][4];
 #pragma unroll
-  for (int u = 0; u < NTW; ++u) {
-    acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int mt = 0; mt < XT_MT; ++mt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) accd[u][v] = 0.0;
-  }
-  const int arow = 8 * q * CP + wave * 16 + li;   // column 8 q of the block, row 16 w + c
-  auto compute = [&](int buf) {
-    u32x4 av[NV];
-    if constexpr (sizeof(TX) == 4) {
-      const uint32_t* xw = reinterpret_cast<const uint32_t*>(xs[buf]) + arow;
+    for (int u = 0; u < NTW; ++u) {
+      acc[mt][u] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        av[0][i] = xw[i * CP];
-        av[1][i] = xw[(4 + i) * CP];
-      }
-    } else {
-      const uint16_t* xh = reinterpret_cast<const uint16_t*>(xs[buf]) + arow;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        av[0][i] = (uint32_t)xh[2 * i * CP] | ((uint32_t)xh[(2 * i + 1) * CP] << 16);
+      for (int v = 0; v < 4; ++v) accd[mt][u][v] = 0.0;
     }
-    bf16x8 xp[NPX];
-    a_parts<TX>(av, xp);
+  // wave w owns row tiles XT_MT w .. XT_MT w + XT_MT - 1; each T part tile read
+  // from LDS serves all of them
+  auto compute = [&](int buf) {
+    bf16x8 xp[XT_MT][NPX];
+#pragma unroll
+    for (int mt = 0; mt < XT_MT; ++mt) {
+      // column 8 q of the block, row 16 (XT_MT w + mt) + c
+      const int arow = 8 * q * CP + (wave * XT_MT + mt) * 16 + li;
+      u32x4 av[NV];
+      if constexpr (sizeof(TX) == 4) {
+        const uint32_t* xw = reinterpret_cast<const uint32_t*>(xs[buf]) + arow;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          av[0][i] = xw[i * CP];
+          av[1][i] = xw[(4 + i) * CP];
+        }
+      } else {
+        const uint16_t* xh = reinterpret_cast<const uint16_t*>(xs[buf]) + arow;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          av[0][i] = (uint32_t)xh[2 * i * CP] | ((uint32_t)xh[(2 * i + 1) * CP] << 16);
+      }
+      a_parts<TX>(av, xp[mt]);
+    }
 #pragma unroll
     for (int u = 0; u < NTW; ++u)
 #pragma unroll
       for (int g = 0; g < NPART; ++g) {
         const bf16x8 tb = __builtin_bit_cast(bf16x8, ts[buf][(g * NTW + u) * 64 + l]);
 #pragma unroll
-        for (int h = 0; h < NPX; ++h)
-          if (h + g < NPART) acc[u] = mfma(xp[h], tb, acc[u]);
+        for (int mt = 0; mt < XT_MT; ++mt)
+#pragma unroll
+          for (int h = 0; h < NPX; ++h)
+            if (h + g < NPART) acc[mt][u] = mfma(xp[mt][h], tb, acc[mt][u]);
       }
   };
   auto flush = [&]() {
 #pragma unroll
-    for (int u = 0; u < NTW; ++u) {
+    for (int mt = 0; mt < XT_MT; ++mt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) accd[u][v] += (double)acc[u][v];
-      acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
+      for (int u = 0; u < NTW; ++u) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) accd[mt][u][v] += (double)acc[mt][u][v];
+        acc[mt][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
   };
   // block kb + 1 goes to LDS (its loads were issued two blocks earlier) and its
   // registers are refilled with block kb + 3 while block kb is multiplied
@@ -470,12 +491,14 @@ __global__ __launch_bounds__(NW * 64) void k_mc_xt(const TX* __restrict__ X, int
   // lane 16 q + c holds rows 4 q + v of the wave's 16, column 16 u + c
   float* __restrict__ out = part + s * pstride;
 #pragma unroll
-  for (int u = 0; u < NTW; ++u)
+  for (int mt = 0; mt < XT_MT; ++mt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = r0 + wave * 16 + 4 * q + v;
-      out[r * (NTW * 16) + 16 * u + li] = (float)accd[u][v];
-    }
+    for (int u = 0; u < NTW; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + (wave * XT_MT + mt) * 16 + 4 * q + v;
+        out[r * (NTW * 16) + 16 * u + li] = (float)accd[mt][u][v];
+      }
 }
 
 // out[j d + r] = alpha sum_s part[s][r PC + j] + beta A + gamma B, the splits
@@ -508,8 +531,10 @@ struct Split {
 Split mc_split(int64_t d, int64_t n) {
   Split sp;
   sp.nrb = (int)((d + RB - 1) / RB);
-  // about 1024 workgroups; a multiple of 8 splits for the XCD mapping
-  int64_t ns = round_up(std::max<int64_t>(8, (1024 + sp.nrb - 1) / sp.nrb), 8);
+  // about 256 workgroups, one per compute unit (fewer, longer column runs
+  // stream better, and the partials to reduce shrink with the split count);
+  // a multiple of 8 splits for the XCD mapping
+  int64_t ns = round_up(std::max<int64_t>(8, (256 + sp.nrb - 1) / sp.nrb), 8);
   ns = std::min<int64_t>(ns, round_up((n + 31) / 32, 8));
   sp.kper = round_up((n + ns - 1) / ns, 32);
   sp.nsplit = (int)ns;
