@@ -270,9 +270,10 @@ void lowrank_destroy(lr_plan plan);
 /* Device workspace in bytes that lowrank_plan (or a server) keeps for this
  * problem: the n-length sampling table, the n x pad16(p) block X^T W, the d x p
  * iterates and the minibatch staging; for LR_CSC also the row-ordered copy of
- * X and its chunk tables (plan creation needs about 12 nnz + sort-scratch bytes
- * more while it builds that copy).  Same checks as lowrank_plan, done on the
- * host only. */
+ * X and its chunk tables, plus the buffers of the inner step's sorted scatter,
+ * which depend on the largest column and are bounded from above here (plan
+ * creation needs about 12 nnz + sort-scratch bytes more while it builds the
+ * row-ordered copy).  Same checks as lowrank_plan, done on the host only. */
 lr_status lowrank_plan_bytes(const lr_matrix* X, int k, int p, const lr_options* opt,
                              size_t* bytes);
 

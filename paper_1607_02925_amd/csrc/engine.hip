@@ -67,6 +67,11 @@ struct lr_plan_s {
   int32_t *sp_head_slot = nullptr, *sp_head_row = nullptr;
   int sp_H = 0;
   double* sp_part = nullptr;
+  // the inner step's scatter in a fixed order (sp_sorted), for up to
+  // bmax x sp_maxnnz contributions
+  bool sp_sorted = false;
+  int sp_maxnnz = 0;
+  lr::SpSortBufs sp_sb{};
   double *Wrm = nullptr, *Grm = nullptr, *Dlrm = nullptr;
   // BF16 matrix-core inner steps: split copies of the difference block (ldD x PC)
   // and of the sampled products (PC x ldC)
@@ -372,8 +377,12 @@ struct lr_plan_s {
           if (sparse) {
             LR_HIP(lr::csc_step_dot(Xs, b, it, scale + (t - t0) * b, Dlrm, C, PC, st, pd));
             LR_HIP(lr::rm_decay(d * PC, Grm, Dlrm, lam_in, eta, st));
-            LR_HIP(lr::csc_step_scatter(Xs, b, it, C, PC, p, sp_head_slot, sp_head_row, sp_H,
-                                        eta, Dlrm, st, pu));
+            if (sp_sorted)
+              LR_HIP(lr::csc_step_scatter_sorted(Xs, b, sp_maxnnz, it, C, PC, p, eta, sp_sb,
+                                                 Dlrm, st, pu));
+            else
+              LR_HIP(lr::csc_step_scatter(Xs, b, it, C, PC, p, sp_head_slot, sp_head_row, sp_H,
+                                          eta, Dlrm, st, pu));
           } else if (bf16_steps) {
             LR_HIP(lr::step_dot_bf16(X, p, b, it, scale + (t - t0) * b, Dh, Dlo, ldD, Ch, Cl,
                                      ldC, PC, st, pd));
@@ -1104,6 +1113,32 @@ lr_status lr_plan_s::sparse_setup() {
   sp_head_row = (int32_t*)hr;
   sp_H = H;
   sp_part = (double*)pt;
+  // the inner step's scatter in a fixed order needs room for bmax x (most
+  // entries in a column) contributions; past the cap it stays with atomics
+  std::vector<int32_t> cph(Xs.n + 1);
+  LR_HIP(hipMemcpyAsync(cph.data(), Xs.cp, (Xs.n + 1) * 4, hipMemcpyDeviceToHost, st));
+  LR_HIP(hipStreamSynchronize(st));
+  int64_t maxnnz = 0;
+  for (int64_t i = 0; i < Xs.n; ++i) maxnnz = std::max<int64_t>(maxnnz, cph[i + 1] - cph[i]);
+  const int64_t tmax = bmax * maxnnz;
+  if (maxnnz >= 1 && tmax <= lr::SP_SORT_CAP) {
+    // the same buffers as lr::sp_sort_bytes counts for plan_bytes
+    void *ki = nullptr, *ko = nullptr, *pi = nullptr, *po = nullptr, *xv = nullptr,
+         *hs2 = nullptr, *ca = nullptr, *fl = nullptr;
+    const int64_t nchs = lr::sp_chunks(tmax);
+    LR_CHECK(keep(&ki, (size_t)tmax * 4));
+    LR_CHECK(keep(&ko, (size_t)tmax * 4));
+    LR_CHECK(keep(&pi, (size_t)tmax * 4));
+    LR_CHECK(keep(&po, (size_t)tmax * 4));
+    LR_CHECK(keep(&xv, (size_t)tmax * 8));
+    LR_CHECK(keep(&hs2, (size_t)(lr::sp_sort_tiles(tmax) + 1) * 256 * 4));
+    LR_CHECK(keep(&ca, (size_t)nchs * 2 * PC * 8));
+    LR_CHECK(keep(&fl, (size_t)nchs * 4));
+    sp_sb = lr::SpSortBufs{(uint32_t*)ki, (uint32_t*)ko, (int32_t*)pi, (int32_t*)po, (double*)xv,
+                           (int32_t*)hs2, (double*)ca, (int32_t*)fl, tmax};
+    sp_maxnnz = (int)maxnnz;
+    sp_sorted = true;
+  }
   return LR_OK;
 }
 
@@ -1187,15 +1222,19 @@ void plan_shape(lr_plan_s* pl, const lr_matrix* Xm, int k, int p, const lr_optio
 }
 
 // Device bytes the compressed-column path keeps besides the carved block: the
-// row-ordered copy (column ids and values), chunk tables, head-row map and the
-// chunk partial sums (at most d + nnz / SP_CHUNK chunks).
+// row-ordered copy (column ids and values), chunk tables, head-row map, the
+// chunk partial sums (at most d + nnz / SP_CHUNK chunks) and, bounded from
+// above with the largest column taken as min(d, nnz) entries, the buffers of
+// the sorted inner-step scatter.
 size_t sparse_extra_bytes(const lr_plan_s* pl) {
   if (!pl->sparse) return 0;
   const int64_t nnz = pl->Xs.nnz, d = pl->d;
   const size_t elt = pl->Xs.dt == LR_F64 ? 8 : pl->Xs.dt == LR_F32 ? 4 : 2;
   const int64_t nch = d + nnz / lr::SP_CHUNK + 1;
+  const int64_t tmax = std::min<int64_t>(pl->bmax * std::max<int64_t>(1, std::min(d, nnz)),
+                                         lr::SP_SORT_CAP);
   return (size_t)nnz * (4 + elt) + (size_t)(d + 1 + nch + 1 + d + 1024) * 4 +
-         (size_t)nch * pl->PC * 8;
+         (size_t)nch * pl->PC * 8 + lr::sp_sort_bytes(tmax, pl->PC);
 }
 }  // namespace
 

@@ -33,6 +33,9 @@ struct CsrView {
   int dt;
 };
 constexpr int SP_CHUNK = 2048;
+// Most contributions (minibatch x the most entries any column stores) for
+// which a plan keeps the buffers of the inner step's sorted scatter.
+constexpr int64_t SP_SORT_CAP = (int64_t)1 << 22;
 
 // Structure checks (flags OR-ed into *bad): 1 = col_ptr not a non-decreasing
 // sequence from 0 to nnz; 2 = a row id outside [0, d) or not increasing within
@@ -74,8 +77,30 @@ hipError_t rm_decay(int64_t count, const double* Grm, double* Dlrm, double lam, 
                     hipStream_t st);
 // Inner step, part 2b: Dlrm[r, c] += eta sum_j X[r, idx[j]] C[j, c], c < p.
 // Rows with head_slot[r] >= 0 (head_row[slot] = r, slot < H) are summed per
-// workgroup in LDS first; all additions to Dlrm are FP64 atomics.
+// workgroup in LDS first; all additions to Dlrm are FP64 atomics (used when
+// the sorted form's buffers would exceed the plan's cap).
 int sp_head_cap(int PC);
+// Inner step, part 2b in a fixed order: the b maxnnz contributions (maxnnz: the
+// most entries any column stores) sorted by row with a stable radix sort, each
+// row's run summed in sample order; no atomics, so the result does not depend
+// on timing.  Device buffers for up to total_max contributions:
+struct SpSortBufs {
+  uint32_t *keys_in, *keys_out;   // total_max each
+  int32_t *pos_in, *pos_out;      // total_max each
+  double* xval;                   // total_max: each contribution's stored value
+  int32_t* hist;                  // 256 x (sp_sort_tiles(total_max) + 1): counts, totals
+  double* carry;                  // sp_chunks(total_max) x 2 x PC
+  int32_t* flags;                 // sp_chunks(total_max)
+  int64_t total_max;
+};
+int64_t sp_chunks(int64_t total);
+int64_t sp_sort_tiles(int64_t total);
+// All device bytes of SpSortBufs for total_max contributions.
+size_t sp_sort_bytes(int64_t total_max, int PC);
+hipError_t csc_step_scatter_sorted(const CscView& X, int64_t b, int maxnnz, const int32_t* idx,
+                                   const double* C, int PC, int p, double eta,
+                                   const SpSortBufs& sb, double* Dlrm, hipStream_t st,
+                                   const Probe& pr = Probe());
 hipError_t csc_step_scatter(const CscView& X, int64_t b, const int32_t* idx, const double* C,
                             int PC, int p, const int32_t* head_slot, const int32_t* head_row,
                             int H, double eta, double* Dlrm, hipStream_t st,

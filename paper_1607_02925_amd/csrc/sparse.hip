@@ -8,10 +8,12 @@
 // row.  X^T W is a per-column gather (deterministic); X T goes through a
 // row-ordered copy of X built once per plan, with long rows cut into chunks
 // whose partial sums are added in chunk order (deterministic, and no single
-// heavy row serialises the pass).  The inner-step update scatters into the
-// rows of its b sampled columns with FP64 atomics, the rows that occur most
-// often summed per workgroup in LDS first: this is the one place whose
-// rounding order depends on timing.
+// heavy row serialises the pass).  The inner-step update adds into the rows
+// of its b sampled columns in a fixed order: the contributions are sorted by
+// row and each row's run is summed in sample order (csc_step_scatter_sorted).
+// Where the b x (largest column) contributions would not fit the plan's cap,
+// the update falls back to FP64 atomics (the rows that occur most often summed
+// per workgroup in LDS first), whose rounding order depends on timing.
 #include "sparse.h"
 
 #include <hip/hip_ext.h>
@@ -273,6 +275,309 @@ __global__ __launch_bounds__(NT) void k_csc_scatter(const TX* __restrict__ v,
   }
 }
 
+// The inner-step scatter in a fixed order.  Contribution t = j maxnnz + kk
+// (sample j, the kk-th stored entry of column idx[j]) adds eta v_k C[j, :] to
+// row ri[k], k = cp[idx[j]] + kk.  The contributions are sorted by row with a
+// stable radix sort (positions whose kk is past the column's entries carry the
+// key `pad` >= d and sort last), so each row's contributions form one run in
+// ascending t.  Each wave sums the runs of SG_CH consecutive sorted
+// contributions in that order; a run wholly inside the chunk is added to its
+// row directly (no other wave touches that row), a run that crosses a chunk
+// boundary leaves its pieces in `carry`, and the workgroup of the chunk where
+// the run starts adds them up in a fixed order.  Nothing depends on timing.
+constexpr int SG_CH = 64;       // sorted contributions per wave
+constexpr int SG_WAVES = 4;     // waves per workgroup of k_sp_runs
+constexpr int SG_PREV = 1;      // the chunk's first run began in an earlier chunk
+constexpr int SG_NEXT = 2;      // the chunk's last run goes on into the next chunk
+constexpr int SG_SINGLE = 4;    // the chunk holds one run only
+
+template <typename TX>
+__global__ __launch_bounds__(NT) void k_sp_keys(const TX* __restrict__ v,
+                                                const int32_t* __restrict__ cp,
+                                                const int32_t* __restrict__ ri,
+                                                const int32_t* __restrict__ idx, int64_t total,
+                                                int maxnnz, uint32_t pad,
+                                                uint32_t* __restrict__ keys,
+                                                int32_t* __restrict__ pos,
+                                                double* __restrict__ xval) {
+  const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (t >= total) return;
+  const int64_t j = t / maxnnz;
+  const int64_t i = idx[j];
+  const int64_t k = cp[i] + (t - j * maxnnz);
+  const bool in = k < cp[i + 1];
+  keys[t] = in ? (uint32_t)ri[k] : pad;
+  xval[t] = in ? ldv(v, k) : 0.0;
+  pos[t] = (int32_t)t;
+}
+
+// Stable least-significant-digit radix sort of (key, position) pairs, 8 bits
+// per pass, in three kernels per pass: digit counts per tile of RS_TILE items;
+// per digit, the exclusive prefix of its counts over the tiles and its total;
+// and a scatter in which each tile starts digit g at (sum of the totals of the
+// digits below g) + (its prefix of g) and ranks its items in index order
+// (within a wave by matching the digit across lanes, across the tile's waves
+// and rounds by counters in LDS).  Integer work only: the order is exact and
+// does not depend on timing.
+constexpr int RS_T = 256, RS_IPT = 8, RS_TILE = RS_T * RS_IPT, RS_W = RS_T / 64;
+constexpr int RS_SCAN_T = 1024, RS_SCAN_PT = 2;   // tiles per thread in k_rs_scan
+constexpr int64_t RS_MAX_TILES = (int64_t)RS_SCAN_T * RS_SCAN_PT;
+
+__global__ __launch_bounds__(RS_T) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t N,
+                                                  int shift, int64_t ntiles,
+                                                  int32_t* __restrict__ hist) {
+  __shared__ int32_t cnt[256];
+  const int t = threadIdx.x;
+  cnt[t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll
+  for (int r = 0; r < RS_IPT; ++r) {
+    const int64_t e = base + r * RS_T + t;
+    if (e < N) atomicAdd(&cnt[(keys[e] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)t * ntiles + blockIdx.x] = cnt[t];
+}
+
+// Digit blockIdx.x: its counts over the tiles (hist row) become their exclusive
+// prefix, and its total goes to tot[digit].  ntiles <= RS_MAX_TILES.
+__global__ __launch_bounds__(RS_SCAN_T) void k_rs_scan(int32_t* __restrict__ hist,
+                                                       int64_t ntiles,
+                                                       int32_t* __restrict__ tot) {
+  __shared__ int32_t part[RS_SCAN_T];
+  const int t = threadIdx.x;
+  int32_t* __restrict__ row = hist + (int64_t)blockIdx.x * ntiles;
+  int32_t h[RS_SCAN_PT];
+  int32_t s = 0;
+#pragma unroll
+  for (int u = 0; u < RS_SCAN_PT; ++u) {
+    const int64_t i = (int64_t)t * RS_SCAN_PT + u;
+    h[u] = i < ntiles ? row[i] : 0;
+    s += h[u];
+  }
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < RS_SCAN_T; off <<= 1) {
+    const int32_t add = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  int32_t run = t > 0 ? part[t - 1] : 0;
+#pragma unroll
+  for (int u = 0; u < RS_SCAN_PT; ++u) {
+    const int64_t i = (int64_t)t * RS_SCAN_PT + u;
+    if (i < ntiles) row[i] = run;
+    run += h[u];
+  }
+  if (t == RS_SCAN_T - 1) tot[blockIdx.x] = part[t];
+}
+
+__global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                     const int32_t* __restrict__ vin, int64_t N,
+                                                     int shift, int64_t ntiles,
+                                                     const int32_t* __restrict__ offs,
+                                                     const int32_t* __restrict__ tot,
+                                                     uint32_t* __restrict__ kout,
+                                                     int32_t* __restrict__ vout) {
+  static_assert(RS_T == 256, "one thread per digit");
+  __shared__ int32_t running[256];
+  __shared__ int32_t wcnt[RS_W][256];
+  const int t = threadIdx.x, wave = t / 64, lane = t % 64;
+  // where digit t of this tile starts: the totals of the digits below t (an
+  // exclusive scan over the 256 totals in LDS) plus this tile's prefix of t
+  const int32_t mine = offs[(int64_t)t * ntiles + blockIdx.x];
+  running[t] = tot[t];
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int32_t add = t >= off ? running[t - off] : 0;
+    __syncthreads();
+    running[t] += add;
+    __syncthreads();
+  }
+  const int32_t below_digits = t > 0 ? running[t - 1] : 0;
+  __syncthreads();
+  running[t] = below_digits + mine;
+  const uint64_t below_mask = (1ull << lane) - 1;
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_IPT; ++r) {
+#pragma unroll
+    for (int w = 0; w < RS_W; ++w) wcnt[w][t] = 0;
+    __syncthreads();
+    const int64_t e = base + r * RS_T + t;
+    const bool valid = e < N;
+    const uint32_t k = valid ? kin[e] : 0u;
+    const int32_t v = valid ? vin[e] : 0;
+    const int dg = (int)((k >> shift) & 255u);
+    uint64_t peers = __ballot(valid);   // valid lanes of this wave with the same digit
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const uint64_t m = __ballot((dg >> bit) & 1);
+      peers &= ((dg >> bit) & 1) ? m : ~m;
+    }
+    const int below = __popcll(peers & below_mask);
+    if (valid && below == 0) wcnt[wave][dg] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int at = running[dg] + below;
+      for (int w = 0; w < wave; ++w) at += wcnt[w][dg];
+      kout[at] = k;
+      vout[at] = v;
+    }
+    __syncthreads();
+    int add = 0;
+#pragma unroll
+    for (int w = 0; w < RS_W; ++w) add += wcnt[w][t];
+    running[t] += add;
+    __syncthreads();
+  }
+}
+
+// Runs of the sorted contributions, one chunk of SG_CH per wave (lane l
+// fetches contribution l of the chunk, lanes c < p then add column c of every
+// contribution in order).  carry[(2 ch + 0) PC + c]: the first run's piece when
+// it began in an earlier chunk; carry[(2 ch + 1) PC + c]: the last run's piece
+// when it goes on into the next chunk and began in this one.
+template <int PC>
+__global__ __launch_bounds__(SG_WAVES * 64) void k_sp_runs(
+    const uint32_t* __restrict__ keys, const int32_t* __restrict__ pos, int64_t total,
+    int maxnnz, const double* __restrict__ xval, const double* __restrict__ C, int p,
+    double eta, uint32_t pad, double* __restrict__ Dlrm, double* __restrict__ carry,
+    int32_t* __restrict__ flags) {
+  const int lane = threadIdx.x % 64;
+  const int64_t ch = (int64_t)blockIdx.x * SG_WAVES + threadIdx.x / 64;
+  const int64_t e0 = ch * SG_CH;
+  if (e0 >= total) return;
+  const int64_t e = e0 + lane;
+  const uint32_t key = e < total ? keys[e] : pad;
+  int jl = 0;
+  double xl = 0.0;
+  if (key != pad) {
+    const int32_t t = pos[e];
+    jl = t / maxnnz;
+    xl = xval[t];
+  }
+  const uint32_t kprev = e0 > 0 ? keys[e0 - 1] : pad;
+  const uint32_t knext = e0 + SG_CH < total ? keys[e0 + SG_CH] : pad;
+  // valid contributions form a prefix of the chunk (pads sort last)
+  const int nv = __popcll(__ballot(key != pad));
+  const int c = lane < PC ? lane : PC - 1;
+  double acc = 0.0;
+  int runs = 0, fl = 0, start = 0;
+  constexpr int U = 8;   // C rows fetched together
+  static_assert(SG_CH % U == 0, "whole batches");
+  // the loop index is the same in every lane, so lane i's values are read
+  // with readlane (a scalar register) rather than a shuffle through LDS
+  auto lane_u32 = [](uint32_t x, int i) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, i);
+  };
+  auto lane_f64 = [](double x, int i) {
+    const uint64_t u = __double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, i);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), i);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+  };
+  // Runs that end inside the chunk and are added to Dlrm directly (not the first
+  // run when it began in the previous chunk, not a run going on into the next
+  // one) are known before the loop; their rows of Dlrm are fetched with each
+  // batch's rows of C, so no read of Dlrm waits inside the loop.
+  // (the shuffle runs in every lane: a lane left out of it would hand its
+  // neighbour nothing)
+  const uint32_t kdown = __shfl_down(key, 1);
+  const uint32_t kn = lane < SG_CH - 1 ? kdown : knext;
+  const uint64_t ends = __ballot(key != pad && kn != key);
+  uint64_t direct = ends;
+  if (nv > 0 && kprev == lane_u32(key, 0)) direct &= direct - 1;   // drop the first run's end
+  if (nv == SG_CH && knext == lane_u32(key, SG_CH - 1)) direct &= ~(1ull << (SG_CH - 1));
+  for (int i0 = 0; i0 < nv; i0 += U) {
+    double cv[U], dv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)   // lanes past nv hold sample 0: an in-bounds row of C
+      cv[u] = C[(int64_t)lane_u32((uint32_t)jl, i0 + u) * PC + c];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      dv[u] = (direct >> (i0 + u)) & 1 ? Dlrm[(int64_t)lane_u32(key, i0 + u) * PC + c] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u;
+      if (i >= nv) break;
+      acc += lane_f64(xl, i) * (eta * cv[u]);
+      if (!((ends >> i) & 1) && i + 1 < SG_CH) continue;
+      // the run of row r ends at i
+      const uint32_t r = lane_u32(key, i);
+      const bool cprev = start == 0 && kprev == r;
+      const bool cnext = i + 1 == SG_CH && knext == r;
+      if (cprev) {
+        fl |= SG_PREV;
+        if (lane < PC) carry[(2 * ch) * PC + lane] = acc;
+      } else if (cnext) {
+        if (lane < PC) carry[(2 * ch + 1) * PC + lane] = acc;
+      } else if (lane < p) {
+        Dlrm[(int64_t)r * PC + lane] = dv[u] + acc;
+      }
+      if (cnext) fl |= SG_NEXT;
+      ++runs;
+      acc = 0.0;
+      start = i + 1;
+    }
+  }
+  if (runs == 1) fl |= SG_SINGLE;
+  if (lane == 0) flags[ch] = fl;
+}
+
+// Runs that cross chunks: the workgroup of the chunk where such a run begins
+// finds the chunk where it ends, sums the pieces (the starting chunk's last
+// piece, then the later chunks' first pieces: NT / PC groups take every
+// (NT / PC)-th chunk, each group in four interleaved partial sums added as
+// (s0 + s1) + (s2 + s3), and the group sums are added in group order) and adds
+// the total to the run's row.
+template <int PC>
+__global__ __launch_bounds__(NT) void k_sp_cross(const uint32_t* __restrict__ keys,
+                                                 int64_t nch, const int32_t* __restrict__ flags,
+                                                 const double* __restrict__ carry, int p,
+                                                 double* __restrict__ Dlrm) {
+  constexpr int G = NT / PC;
+  __shared__ int64_t s_end;
+  __shared__ double gsum[G * PC];
+  const int64_t c0 = blockIdx.x;
+  const int f = flags[c0];
+  if (!(f & SG_NEXT) || ((f & SG_SINGLE) && (f & SG_PREV))) return;
+  const int t = threadIdx.x;
+  // the run goes through every chunk that holds only it and goes on again
+  if (t == 0) s_end = nch;
+  __syncthreads();
+  for (int64_t base = c0 + 1; base < nch; base += NT) {
+    const int64_t c2 = base + t;
+    if (c2 < nch && (flags[c2] & (SG_SINGLE | SG_NEXT)) != (SG_SINGLE | SG_NEXT))
+      atomicMin((unsigned long long*)&s_end, (unsigned long long)c2);
+    __syncthreads();
+    if (s_end < nch) break;
+    __syncthreads();
+  }
+  const int64_t c1 = s_end < nch ? s_end : nch - 1;   // chunk where the run ends
+  const int g = t / PC, col = t % PC;
+  if (g < G) {   // NT need not be a multiple of PC
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t c2 = c0 + 1 + g;
+    for (; c2 + 3 * G <= c1; c2 += 4 * G) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s4[u] += carry[(2 * (c2 + u * G)) * PC + col];
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u, c2 += G)   // at most three left per group
+      if (c2 <= c1) s4[u] += carry[(2 * c2) * PC + col];
+    gsum[g * PC + col] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+  }
+  __syncthreads();
+  if (t < p) {
+    double tot = carry[(2 * c0 + 1) * PC + t];
+    for (int h = 0; h < G; ++h) tot += gsum[h * PC + t];
+    const uint32_t r = keys[c0 * SG_CH + SG_CH - 1];
+    Dlrm[(int64_t)r * PC + t] += tot;
+  }
+}
+
 }  // namespace
 
 template <typename K, typename... A>
@@ -424,6 +729,50 @@ hipError_t csc_step_dot(const CscView& X, int64_t b, const int32_t* idx, const d
 hipError_t rm_decay(int64_t count, const double* Grm, double* Dlrm, double lam, double eta,
                     hipStream_t st) {
   k_rm_decay<<<blocks(count), NT, 0, st>>>(count, Grm, Dlrm, lam, eta);
+  return hipGetLastError();
+}
+
+int64_t sp_chunks(int64_t total) { return (total + SG_CH - 1) / SG_CH; }
+
+int64_t sp_sort_tiles(int64_t total) { return (total + RS_TILE - 1) / RS_TILE; }
+
+size_t sp_sort_bytes(int64_t total_max, int PC) {
+  return (size_t)total_max * 24 + (size_t)(sp_sort_tiles(total_max) + 1) * 256 * 4 +
+         (size_t)sp_chunks(total_max) * (2 * PC * 8 + 4);
+}
+
+hipError_t csc_step_scatter_sorted(const CscView& X, int64_t b, int maxnnz, const int32_t* idx,
+                                   const double* C, int PC, int p, double eta,
+                                   const SpSortBufs& sb, double* Dlrm, hipStream_t st,
+                                   const Probe& pr) {
+  const int64_t total = b * (int64_t)maxnnz;
+  if (p > PC || maxnnz < 1 || b < 1 || total > sb.total_max || X.d >= (int64_t)UINT32_MAX ||
+      sp_sort_tiles(total) > RS_MAX_TILES)
+    return hipErrorInvalidValue;
+  const uint32_t pad = (uint32_t)X.d;   // above every row id, inside key_bits(d + 1)
+  SP_DISPATCH_DT(X.dt, TX,
+                 k_sp_keys<TX><<<blocks(total), NT, 0, st>>>((const TX*)X.v, X.cp, X.ri, idx,
+                                                             total, maxnnz, pad, sb.keys_in,
+                                                             sb.pos_in, sb.xval));
+  // radix passes over the bits of d + 1, ping-ponging between the buffer pairs
+  const int64_t ntiles = sp_sort_tiles(total);
+  uint32_t *ka = sb.keys_in, *kb = sb.keys_out;
+  int32_t *pa = sb.pos_in, *pb = sb.pos_out;
+  for (int shift = 0; shift < key_bits(X.d + 1); shift += 8) {
+    k_rs_hist<<<(unsigned)ntiles, RS_T, 0, st>>>(ka, total, shift, ntiles, sb.hist);
+    k_rs_scan<<<256, RS_SCAN_T, 0, st>>>(sb.hist, ntiles, sb.hist + 256 * ntiles);
+    k_rs_scatter<<<(unsigned)ntiles, RS_T, 0, st>>>(ka, pa, total, shift, ntiles, sb.hist,
+                                                    sb.hist + 256 * ntiles, kb, pb);
+    std::swap(ka, kb);
+    std::swap(pa, pb);
+  }
+  const int64_t nch = sp_chunks(total);
+  SP_DISPATCH_PC(PC, PCT, {
+    launch_sp(k_sp_runs<PCT>, dim3((unsigned)((nch + SG_WAVES - 1) / SG_WAVES)),
+              dim3(SG_WAVES * 64), st, pr, (const uint32_t*)ka, (const int32_t*)pa, total, maxnnz,
+              (const double*)sb.xval, C, p, eta, pad, Dlrm, sb.carry, sb.flags);
+    k_sp_cross<PCT><<<(unsigned)nch, NT, 0, st>>>(ka, nch, sb.flags, sb.carry, p, Dlrm);
+  });
   return hipGetLastError();
 }
 

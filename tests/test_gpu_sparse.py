@@ -2,8 +2,10 @@
 
 Bit-exact: the structure checks, column norms and sampling table.  Within
 rounding (different summation orders): passes, inner solves and whole solves.
-The inner-step update of the sparse path adds with FP64 atomics, so its
-rounding order varies from run to run; the tolerances below cover that.
+The inner-step update adds each row's contributions in a fixed order (sorted by
+row, then by sample), so repeated runs are bitwise equal; a plan whose
+minibatch times its largest column passes the sorted form's cap adds with FP64
+atomics instead, whose rounding order varies (tested against the oracle only).
 """
 import numpy as np
 import pytest
@@ -193,3 +195,77 @@ def test_full_size_pass_table_and_epoch(torch_cuda):
     Wg = Wg.cpu().numpy()
     assert np.max(np.abs(Wg - Wo)) <= 1e-10 * np.max(np.abs(Wo))
     np.testing.assert_allclose(res_g, res_o, rtol=1e-8)
+
+
+def _fixed_epochs(sp, storage, p, b_req, seed, epochs=2):
+    """Inner solves under fixed epochs on the GPU (twice) and in the oracle."""
+    import torch
+    X = oracle.decode(sp, storage)
+    d = sp["d"]
+    pl = plan(sp, 2, p, seed=seed)
+    pl.prepare()
+    _, qc = oracle.build_table(oracle.column_sq_norms(X))
+    S = oracle.cholqr2(np.random.default_rng(3).standard_normal((d, p)))[0]
+    lam1 = np.linalg.eigvalsh((X @ X.T).toarray())[-1]
+    lam = 1.1 * lam1
+    fro2 = float(X.multiply(X).sum())
+    b, eta, m = oracle.solver_constants(fro2, lam1, lam, 0.1 * lam1, sp["n"], batch=b_req)
+    runs = [pl.svrg_solve(torch.from_numpy(S).cuda(), lam, eta, m, b, 5, epochs)
+            for _ in range(2)]
+    Wo, _, res_o = oracle.svrg_solve(X, qc, S, lam, eta, m, b, 0.0, seed, 5, 60,
+                                     fixed_epochs=epochs)
+    return runs, Wo, res_o, (m, b)
+
+
+def test_inner_steps_bitwise_repeatable(torch_cuda):
+    """The same inner solve twice on a Zipf-row matrix (rows shared by many
+    sampled columns, the sorted scatter's long runs): bitwise equal, and
+    against the oracle."""
+    import torch
+    sp = sparse.zipf_csc(600, 5000, 16, seed=11)
+    runs, Wo, res_o, mb = _fixed_epochs(sp, "csc-f32", 8, 512, 99)
+    (W1, r1), (W2, r2) = runs
+    print("m, b =", mb, "residuals", r1, res_o, flush=True)
+    assert torch.equal(W1, W2)
+    assert np.array_equal(np.asarray(r1), np.asarray(r2))
+    W = W1.cpu().numpy()
+    assert np.max(np.abs(W - Wo)) <= 1e-9 * np.max(np.abs(Wo))
+    np.testing.assert_allclose(r1, res_o, rtol=1e-7)
+
+
+@pytest.mark.parametrize("p", [5, 33])
+def test_ragged_columns_inner_steps(torch_cuda, p):
+    """Columns of 0..12 entries (empty ones included), so the sorted scatter
+    pads the short columns' slots: bitwise repeatable and against the oracle,
+    for p in one and in three 16-column slices."""
+    import torch
+    sp = ragged_csc(300, 4000, 21, max_nnz=12)
+    runs, Wo, res_o, mb = _fixed_epochs(sp, "csc-f32", p, 1024, 17)
+    (W1, r1), (W2, r2) = runs
+    print("p %d m, b = %s residuals %s %s" % (p, mb, r1, res_o), flush=True)
+    assert torch.equal(W1, W2)
+    W = W1.cpu().numpy()
+    assert np.max(np.abs(W - Wo)) <= 1e-9 * np.max(np.abs(Wo))
+    np.testing.assert_allclose(r1, res_o, rtol=1e-7)
+
+
+def test_wide_column_atomic_scatter(torch_cuda):
+    """One column holding every row makes minibatch x largest column pass the
+    sorted scatter's cap (4000 x 1500 > 2^22), so the plan adds with atomics:
+    against the oracle within rounding."""
+    sp = ragged_csc(1500, 4000, 23, max_nnz=8)
+    cp = sp["col_ptr"].astype(np.int64)
+    # replace column 5 by a column with all 1500 rows
+    rows = [sp["row_idx"][cp[i]:cp[i + 1]] for i in range(sp["n"])]
+    vals = [sp["values"][cp[i]:cp[i + 1]] for i in range(sp["n"])]
+    rows[5] = np.arange(1500, dtype=np.int32)
+    vals[5] = (np.random.default_rng(5).standard_normal(1500) * 0.05).astype(np.float32)
+    counts = np.array([len(r) for r in rows])
+    sp = dict(sp, nnz=int(counts.sum()), row_idx=np.concatenate(rows).astype(np.int32),
+              values=np.concatenate(vals).astype(np.float32),
+              col_ptr=np.concatenate([[0], np.cumsum(counts)]).astype(np.int32))
+    runs, Wo, res_o, mb = _fixed_epochs(sp, "csc-f32", 8, 2048, 29, epochs=1)
+    W = runs[0][0].cpu().numpy()
+    print("m, b =", mb, "residuals", runs[0][1], res_o, flush=True)
+    assert np.max(np.abs(W - Wo)) <= 1e-9 * np.max(np.abs(Wo))
+    np.testing.assert_allclose(runs[0][1], res_o, rtol=1e-7)
