@@ -70,8 +70,9 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: HBM budget (GB)")
     ap.add_argument("--rate", type=float, default=50.0, help="serve: arrivals per second")
     ap.add_argument("--forms", default="seq,closed,open,mc",
-                    help="serve: comma list of seq (FP32 one at a time), closed, open, "
-                         "mc (closed loop with matrix-core inner steps)")
+                    help="serve: comma list of seq (FP32 one at a time), seq_mc (one at a "
+                         "time, matrix-core form), closed, open, mc (closed and open loops in "
+                         "the matrix-core form)")
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true",
@@ -464,6 +465,9 @@ def serve_bench(args, dev):
     if "seq" in forms:
         out["fp32_per_request"], seq_outs = serve_run(reqs, X32, 1, budget)
         log("serve fp32 per-request: %s" % json.dumps(out["fp32_per_request"]))
+    if "seq_mc" in forms:   # one request at a time, each in the matrix-core form
+        out["matrix_core_per_request"], _ = serve_run(reqs, Xown, 1, budget, matrix_core=True)
+        log("serve matrix-core per-request: %s" % json.dumps(out["matrix_core_per_request"]))
     if "closed" in forms:
         out["batched_closed"], closed_outs = serve_run(reqs, Xown, args.slots, budget)
         log("serve batched closed loop: %s" % json.dumps(out["batched_closed"]))
@@ -507,8 +511,9 @@ def serve_bench(args, dev):
             out["speedup_matrix_core_batched_vs_fp32_per_request"] = \
                 out["batched_closed_matrix_core"]["solves_per_s"] / \
                 out["fp32_per_request"]["solves_per_s"]
-    failed = [name for name in ("fp32_per_request", "batched_closed", "batched_open",
-                                "batched_closed_matrix_core", "batched_open_matrix_core")
+    failed = [name for name in ("fp32_per_request", "matrix_core_per_request", "batched_closed",
+                                "batched_open", "batched_closed_matrix_core",
+                                "batched_open_matrix_core")
               if name in out and out[name]["failed"]]
     out["consistent"] = (not failed and out.get("alone_equals_mix", True) and
                          out.get("matrix_core_agrees", True) and

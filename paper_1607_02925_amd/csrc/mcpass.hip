@@ -535,7 +535,9 @@ Split mc_split(int64_t d, int64_t n) {
   // stream better, and the partials to reduce shrink with the split count);
   // a multiple of 8 splits for the XCD mapping
   int64_t ns = round_up(std::max<int64_t>(8, (256 + sp.nrb - 1) / sp.nrb), 8);
-  ns = std::min<int64_t>(ns, round_up((n + 31) / 32, 8));
+  // and at least 256 columns per split, so a short X does not leave most of the
+  // pass to the reduce of many one-block partials
+  ns = std::min<int64_t>(ns, round_up(std::max<int64_t>(1, (n + 255) / 256), 8));
   sp.kper = round_up((n + ns - 1) / ns, 32);
   sp.nsplit = (int)ns;
   return sp;
