@@ -80,6 +80,14 @@ __device__ __forceinline__ float f4get(const float4& v, int s) {
   return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
 }
 
+// Orders a wave's LDS accesses around it (a wave's own LDS operations complete
+// in issue order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Sum the NW waves' accumulators (NT 16x16 tiles each) into red[0 .. NT*256)
 // in wave order, one tile at a time through NW*256 slots; element (i, j) of
 // tile u lands at red[u * 256 + i * 16 + j].
@@ -205,10 +213,16 @@ __global__ __launch_bounds__(NW * 64) void k_sdot_f32(const TX* __restrict__ X, 
 // them all); the new Dl (FP64, tile-major, the layout of the FP64 path) is
 // also rounded into the FP32 tile for the next step.  The NW waves split the
 // samples (indices staged in LDS, padded to a multiple of 16 with a valid
-// column; C32 holds zero rows past b); two register stages; rows past d read
-// row d - 1 (not stored).  The grid (a multiple of 8 tiles) is remapped so
-// each XCD owns a contiguous run of row tiles.
-template <typename TX, int NW, int G, int NT, int KS>
+// column; C32 holds zero rows past b); two register stages.  A block of 16
+// samples is fetched with one load per lane: lane l takes rows 4 (l % 4) ..
+// + 3 of the tile from sample l / 4 (16 contiguous bytes of FP32 X, 8 of
+// BF16 X; VEC moves a piece past d back to rows d - 4 .. d - 1, the scalar
+// form reads rows past d as zero), and the wave turns the 16 x 16 block
+// around through its own LDS tile (two, alternating) into the matrix-core
+// operand order, row c and samples 4 q .. 4 q + 3 for lane 16 q + c.  Rows
+// past d are not stored.  The grid (a multiple of 8 tiles) is remapped so each XCD owns a
+// contiguous run of row tiles.
+template <typename TX, int NW, int G, int NT, int KS, bool VEC>
 __global__ __launch_bounds__(NW * 64) void k_supd_f32(const TX* __restrict__ X, int64_t ld,
                                                       int64_t d, int64_t b,
                                                       const int32_t* __restrict__ idx,
@@ -218,9 +232,11 @@ __global__ __launch_bounds__(NW * 64) void k_supd_f32(const TX* __restrict__ X, 
                                                       double* __restrict__ Dl,
                                                       float* __restrict__ D32, double lam,
                                                       double eta) {
+  constexpr int XTP = 20;   // pitch of a transpose tile: the 64 lanes' writes meet 64 banks
   __shared__ double red[NT * 256];
   __shared__ double slots[NW * 256];
   __shared__ int sidx[KS32];
+  __shared__ __align__(16) float xtr[NW][2][16 * XTP];
   const int t = threadIdx.x, wave = t / 64, l = t % 64, c = l % 16, q = l / 16;
   const int64_t tile = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
   const int64_t r0 = tile * 16;
@@ -243,60 +259,82 @@ __global__ __launch_bounds__(NW * 64) void k_supd_f32(const TX* __restrict__ X, 
   const int64_t bpad = (b + 15) / 16 * 16;
   for (int64_t e = t; e < bpad; e += NW * 64) sidx[e] = idx[e < b ? e : 0];
   __syncthreads();
-  const TX* __restrict__ xrow = X + min(r0 + c, d - 1);
+  const int lj = l >> 2, lr = 4 * (l & 3);   // this lane's sample and first row in a block
+  const int64_t rr = r0 + lr;
+  const int64_t rl = VEC && rr + 4 > d ? d - 4 : rr;
   f32x4 acc[NT];
 #pragma unroll
   for (int v = 0; v < NT; ++v) acc[v] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int64_t nblk = bpad / 16;
   const int64_t bpw = (nblk + NW - 1) / NW;
   const int64_t b0 = wave * bpw, b1 = min(nblk, b0 + bpw);
-  const int* __restrict__ sq = sidx + 4 * q;
   struct Stage {
-    float x[G][4];
-    float4 m[G][NT];
+    float4 x[G];
+    float4 m[G][NT][KS];   // the partials of C, added where they are used
   };
   auto load = [&](Stage& S, int64_t g) {
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       const int64_t blk = min(g + i, b1 - 1);
-      const int* __restrict__ si = sq + blk * 16;
+      const TX* __restrict__ col = X + (int64_t)sidx[blk * 16 + lj] * ld;
+      S.x[i] = VEC ? load4f<TX, true>(col, rl) : load4ftail<TX>(col, rr, d);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) S.x[i][s] = xload(xrow + (int64_t)si[s] * ld);
+      for (int v = 0; v < NT; ++v)
 #pragma unroll
-      for (int v = 0; v < NT; ++v) {
-        float4 m = tile32(C32, blk, u0 + v, NS, l);
-#pragma unroll
-        for (int z = 1; z < KS; ++z) {
-          const float4 y = tile32(C32 + z * cstride, blk, u0 + v, NS, l);
-          m.x += y.x;
-          m.y += y.y;
-          m.z += y.z;
-          m.w += y.w;
-        }
-        S.m[i][v] = m;
-      }
+        for (int z = 0; z < KS; ++z) S.m[i][v][z] = tile32(C32 + z * cstride, blk, u0 + v, NS, l);
     }
   };
-  auto compute = [&](const Stage& S, int64_t g) {
+  auto compute = [&](const Stage& S, int64_t g, bool checked) {
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      if (g + i >= b1) break;
+      if (checked && g + i >= b1) break;
+      float* __restrict__ wt = xtr[wave][(g + i) & 1];
+      wt[(lr + 0) * XTP + lj] = S.x[i].x;
+      wt[(lr + 1) * XTP + lj] = S.x[i].y;
+      wt[(lr + 2) * XTP + lj] = S.x[i].z;
+      wt[(lr + 3) * XTP + lj] = S.x[i].w;
+      wave_sync();
+      const float4 a = *reinterpret_cast<const float4*>(wt + c * XTP + 4 * q);
+      wave_sync();
+      float4 cm[NT];
+#pragma unroll
+      for (int v = 0; v < NT; ++v) {
+        cm[v] = S.m[i][v][0];
+#pragma unroll
+        for (int z = 1; z < KS; ++z) {
+          cm[v].x += S.m[i][v][z].x;
+          cm[v].y += S.m[i][v][z].y;
+          cm[v].z += S.m[i][v][z].z;
+          cm[v].w += S.m[i][v][z].w;
+        }
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int v = 0; v < NT; ++v) acc[v] = mfma32(S.x[i][s], f4get(S.m[i][v], s), acc[v]);
+        for (int v = 0; v < NT; ++v) acc[v] = mfma32(f4get(a, s), f4get(cm[v], s), acc[v]);
     }
   };
   if (b0 < b1) {
+    // whole pairs of stages first, with no branch between a stage's loads and
+    // the work before its use (a guarded use would let the compiler move the
+    // loads down to it, and the next stage's loads would no longer overlap)
     Stage A, B;
     load(A, b0);
-    for (int64_t g = b0; g < b1; g += 2 * G) {
+    int64_t g = b0;
+    for (; g + 2 * G <= b1; g += 2 * G) {
       load(B, g + G);
       __builtin_amdgcn_sched_barrier(0);
-      compute(A, g);
+      compute(A, g, false);
       load(A, g + 2 * G);
       __builtin_amdgcn_sched_barrier(0);
-      compute(B, g + G);
+      compute(B, g + G, false);
+    }
+    if (g < b1) {
+      compute(A, g, true);
+      if (g + G < b1) {
+        load(B, g + G);
+        compute(B, g + G, true);
+      }
     }
   }
   waves_sum32<NW, NT>(red, slots, acc, q, c);
@@ -347,8 +385,14 @@ void supd_launch(const XView& X, int p, int NS, int64_t b, const int32_t* idx, c
                  const double* G, double* Dl, float* D32, double lam, double eta, hipStream_t st,
                  const Probe& pr) {
   const dim3 grid((unsigned)(((X.d + 15) / 16 + 7) / 8 * 8), (unsigned)(NS / NT));
-  launch32(k_supd_f32<TX, 16, 1, NT, KS>, grid, dim3(1024), st, pr, (const TX*)X.v, X.ld, X.d, b,
-           idx, C32, (b + 15) / 16 * 16 * (NS * 16), p, NS, G, Dl, D32, lam, eta);
+  // 16-byte (FP32) or 8-byte (BF16) pieces of 4 rows: aligned columns, d a multiple of 4
+  const bool vec = X.ld % 4 == 0 && X.d % 4 == 0 && (uintptr_t)X.v % (4 * sizeof(TX)) == 0;
+  if (vec)
+    launch32(k_supd_f32<TX, 16, 1, NT, KS, true>, grid, dim3(1024), st, pr, (const TX*)X.v, X.ld,
+             X.d, b, idx, C32, (b + 15) / 16 * 16 * (NS * 16), p, NS, G, Dl, D32, lam, eta);
+  else
+    launch32(k_supd_f32<TX, 16, 1, NT, KS, false>, grid, dim3(1024), st, pr, (const TX*)X.v, X.ld,
+             X.d, b, idx, C32, (b + 15) / 16 * 16 * (NS * 16), p, NS, G, Dl, D32, lam, eta);
 }
 
 template <typename TX, int KS>
