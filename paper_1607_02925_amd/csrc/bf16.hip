@@ -170,15 +170,37 @@ __global__ __launch_bounds__(NW * 64) void k_sdot_bf16(
   }
 }
 
+// v from lane l ^ 2 of the same quad of lanes (DPP quad_perm [2, 3, 0, 1]).
+__device__ __forceinline__ uint32_t quad_xor2(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);
+}
+
+// Orders a wave's LDS accesses around it (a wave's own LDS operations complete
+// in issue order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // U = X_B (Ch + Cl)^T for 16 rows x NTW slices; Dl <- Dl - eta (G + lam Dl - U)
 // for r < d, j < p, and the new Dl is split into Dh/Dlo.  The NW waves split
 // the samples in 32-sample blocks; the indices are staged in LDS, padded to a
 // multiple of 32 with a valid column (the split C tiles hold zeros past b), so
-// every block is whole.  Two register stages as in k_sdot_bf16; rows past d
-// read row d - 1 (their results are not stored).  The grid (a multiple of 8
-// tiles) is remapped so that each XCD owns a contiguous run of row tiles and
-// the pieces of a gathered column's cache line meet in one L2.
-template <int NW, int NTW, int G>
+// every block is whole.  A block comes in with one 16-byte load per lane: lane
+// l takes rows 8 (l % 2) .. + 7 of the row tile from sample l / 2 (VEC moves a
+// piece past d back to rows d - 8 .. d - 1, the scalar form reads rows past d
+// as zero; rows past d are not stored).  Lanes l and l ^ 2 (samples 2 m and
+// 2 m + 1) swap half their rows by DPP so that each holds four words (row,
+// samples 2 m, 2 m + 1), which the wave writes into its own LDS tile (two,
+// alternating; rows of 16 words at a pitch of 20, so the 64 lanes' writes meet
+// 64 banks) and reads back in the matrix-core operand order: row l % 16,
+// samples 8 (l / 16) .. + 7 as one 16-byte read.  Two register stages, taken
+// in whole pairs without a branch so that the next stage's loads stay ahead
+// of the current stage's work.  The grid (a multiple of 8 tiles) is remapped
+// so that each XCD owns a contiguous run of row tiles and the pieces of a
+// gathered column's cache line meet in one L2.
+template <int NW, int NTW, int G, bool VEC>
 __global__ __launch_bounds__(NW * 64) void k_supd_bf16(
     const uint16_t* __restrict__ X, int64_t ld, int64_t d, int64_t b,
     const int32_t* __restrict__ idx, const uint16_t* __restrict__ Ch,
@@ -186,8 +208,10 @@ __global__ __launch_bounds__(NW * 64) void k_supd_bf16(
     double* __restrict__ Dl, uint16_t* __restrict__ Dh, uint16_t* __restrict__ Dlo,
     double lam, double eta) {
   constexpr int EPT = (NTW * 256 + NW * 64 - 1) / (NW * 64);
+  constexpr int XTP = 20;   // words per row of a transpose tile
   __shared__ double slots[NW * NTW * 256];
   __shared__ int sidx[KST];
+  __shared__ __align__(16) uint32_t xtr[NW][2][16 * XTP];
   const int t = threadIdx.x, wave = t / 64, l = t % 64, li = l % 16, q = l / 16;
   const int NS = PC / 16;
   const int64_t tile = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
@@ -211,14 +235,18 @@ __global__ __launch_bounds__(NW * 64) void k_supd_bf16(
   const int64_t bpad = (b + 31) / 32 * 32;
   for (int64_t e = t; e < bpad; e += NW * 64) sidx[e] = idx[e < b ? e : 0];
   __syncthreads();
-  const uint16_t* __restrict__ xrow = X + min(r0 + li, d - 1);
+  const int lj = l >> 1, lh = 8 * (l & 1);   // this lane's sample and first row in a block
+  const int64_t rr = r0 + lh;
+  const int64_t rl = VEC && rr + 8 > d ? d - 8 : rr;
+  // after the exchange: rows wr0 .. wr0 + 3 of the sample pair wm
+  const bool even = (l & 2) == 0;
+  const int wr0 = lh + (even ? 0 : 4), wm = lj >> 1;
   f32x4 ah[NTW], al[NTW];
 #pragma unroll
   for (int u = 0; u < NTW; ++u) ah[u] = al[u] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int64_t nkb = bpad / 32;
   const int64_t kpw = (nkb + NW - 1) / NW;
   const int64_t k0 = wave * kpw, k1 = min(nkb, k0 + kpw);
-  const int* __restrict__ sq = sidx + 8 * q;
   struct Stage {
     uint4 xa[G], ch[G][NTW], cl[G][NTW];
   };
@@ -226,13 +254,8 @@ __global__ __launch_bounds__(NW * 64) void k_supd_bf16(
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       const int64_t kb = min(g + i, k1 - 1);
-      const int* __restrict__ si = sq + kb * 32;
-      uint32_t w[4];
-#pragma unroll
-      for (int h = 0; h < 4; ++h)
-        w[h] = (uint32_t)xrow[(int64_t)si[2 * h] * ld] |
-               ((uint32_t)xrow[(int64_t)si[2 * h + 1] * ld] << 16);
-      S.xa[i] = make_uint4(w[0], w[1], w[2], w[3]);
+      const uint16_t* __restrict__ col = X + (int64_t)sidx[kb * 32 + lj] * ld;
+      S.xa[i] = VEC ? load8full<true>(col, rl) : load8tail(col, rr, d);
 #pragma unroll
       for (int u = 0; u < NTW; ++u) {
         S.ch[i][u] = tile_b(Ch, kb, u, NS, l);
@@ -240,27 +263,49 @@ __global__ __launch_bounds__(NW * 64) void k_supd_bf16(
       }
     }
   };
-  auto compute = [&](const Stage& S, int64_t g) {
+  auto compute = [&](const Stage& S, int64_t g, bool checked) {
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      if (g + i >= k1) break;
+      if (checked && g + i >= k1) break;
+      // words (row, samples 2 wm and 2 wm + 1): the even lane of a pair keeps
+      // its first four rows and takes its partner's, the odd lane the last four
+      const uint4 w = S.xa[i];
+      const uint32_t r0w = quad_xor2(even ? w.z : w.x), r1w = quad_xor2(even ? w.w : w.y);
+      const uint32_t a0 = even ? w.x : r0w, a1 = even ? w.y : r1w;   // sample 2 wm
+      const uint32_t b0 = even ? r0w : w.z, b1 = even ? r1w : w.w;   // sample 2 wm + 1
+      uint32_t* __restrict__ wt = xtr[wave][(g + i) & 1];
+      wt[(wr0 + 0) * XTP + wm] = (a0 & 0xFFFFu) | (b0 << 16);
+      wt[(wr0 + 1) * XTP + wm] = (a0 >> 16) | (b0 & 0xFFFF0000u);
+      wt[(wr0 + 2) * XTP + wm] = (a1 & 0xFFFFu) | (b1 << 16);
+      wt[(wr0 + 3) * XTP + wm] = (a1 >> 16) | (b1 & 0xFFFF0000u);
+      wave_sync();
+      const uint4 xa = *reinterpret_cast<const uint4*>(wt + li * XTP + 4 * q);
+      wave_sync();
 #pragma unroll
       for (int u = 0; u < NTW; ++u) {
-        ah[u] = mfma_bf16(S.xa[i], S.ch[i][u], ah[u]);
-        al[u] = mfma_bf16(S.xa[i], S.cl[i][u], al[u]);
+        ah[u] = mfma_bf16(xa, S.ch[i][u], ah[u]);
+        al[u] = mfma_bf16(xa, S.cl[i][u], al[u]);
       }
     }
   };
   if (k0 < k1) {
     Stage A, B;
     load(A, k0);
-    for (int64_t g = k0; g < k1; g += 2 * G) {
+    int64_t g = k0;
+    for (; g + 2 * G <= k1; g += 2 * G) {
       load(B, g + G);
       __builtin_amdgcn_sched_barrier(0);
-      compute(A, g);
+      compute(A, g, false);
       load(A, g + 2 * G);
       __builtin_amdgcn_sched_barrier(0);
-      compute(B, g + G);
+      compute(B, g + G, false);
+    }
+    if (g < k1) {
+      compute(A, g, true);
+      if (g + G < k1) {
+        load(B, g + G);
+        compute(B, g + G, true);
+      }
     }
   }
   double* mine = slots + wave * (NTW * 256);
@@ -349,10 +394,16 @@ hipError_t step_update_bf16(const XView& X, int p, int64_t b, const int32_t* idx
       ldC % 32 || ldC < pad_to(b, 32) || (uintptr_t)Ch % 16 || (uintptr_t)Cl % 16)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)(((X.d + 15) / 16 + 7) / 8 * 8), 1);
+  // 16-byte pieces of 8 rows: aligned columns, d a multiple of 8
+  const bool vec = X.ld % 8 == 0 && X.d % 8 == 0 && (uintptr_t)X.v % 16 == 0;
   BF_DISPATCH_NTW(PC / 16, NTW, {
     constexpr int GB = NTW <= 2 ? 2 : 1;
-    launch_bf(k_supd_bf16<8, NTW, GB>, grid, dim3(512), st, pr, (const uint16_t*)X.v, X.ld, X.d,
-              b, idx, Ch, Cl, PC, p, G, Dl, Dh, Dlo, lam, eta);
+    if (vec)
+      launch_bf(k_supd_bf16<8, NTW, GB, true>, grid, dim3(512), st, pr, (const uint16_t*)X.v,
+                X.ld, X.d, b, idx, Ch, Cl, PC, p, G, Dl, Dh, Dlo, lam, eta);
+    else
+      launch_bf(k_supd_bf16<8, NTW, GB, false>, grid, dim3(512), st, pr, (const uint16_t*)X.v,
+                X.ld, X.d, b, idx, Ch, Cl, PC, p, G, Dl, Dh, Dlo, lam, eta);
   });
   return hipGetLastError();
 }
