@@ -870,11 +870,52 @@ __global__ __launch_bounds__(NT) void k_reduce_y(const double* __restrict__ part
   }
 }
 
+// Four entries of one column from row r as FP32 (exact for FP32 and BF16 X):
+// VEC reads rows r .. r + 3 (all < d) with one load, the scalar form reads rows
+// past d as zero (addresses clamped to row d - 1).
+template <typename TX, bool VEC>
+__device__ __forceinline__ float4 col4(const TX* __restrict__ col, int64_t r, int64_t d) {
+  static_assert(sizeof(TX) < 8, "FP32 or BF16 storage");
+  if constexpr (VEC && sizeof(TX) == 4) {
+    return *reinterpret_cast<const float4*>(col + r);
+  } else if constexpr (VEC) {
+    const uint2 a = *reinterpret_cast<const uint2*>(col + r);
+    return make_float4(__uint_as_float(a.x << 16), __uint_as_float(a.x & 0xFFFF0000u),
+                       __uint_as_float(a.y << 16), __uint_as_float(a.y & 0xFFFF0000u));
+  } else {
+    float v[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float x = (float)ldx(col, min(r + s, d - 1));
+      v[s] = r + s < d ? x : 0.f;
+    }
+    return make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+__device__ __forceinline__ float f4at(const float4& v, int s) {
+  return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
+}
+
+// Orders a wave's LDS accesses around it (a wave's own LDS operations complete
+// in issue order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Inner-step update for a tile of 16 rows and the 16-column slice nt = blockIdx.y:
 // Dl <- Dl - eta (G + lam Dl - U),  U[r, j] = sum_s X[r, idx[s]] C[s * PC + j].
 // The NW waves split the b samples (indices staged in LDS) and load G sample
-// blocks ahead.
-template <typename TX, int NW, int G, int PC, int NTW, int KS, bool DEFL = false>
+// blocks ahead.  For FP32 and BF16 X a block of 16 samples comes in with one
+// load per lane (lane l: rows 4 (l % 4) .. + 3 of the tile from sample l / 4;
+// VEC moves a piece past d back to rows d - 4 .. d - 1, the scalar form reads
+// rows past d as zero) and the wave turns it around through its own LDS tile
+// (two, alternating; pitch 20 floats, so the 64 lanes' writes meet 64 banks)
+// into the matrix-core operand order; FP64 X is gathered entry by entry.
+template <typename TX, int NW, int G, int PC, int NTW, int KS, bool DEFL = false,
+          bool VEC = false>
 __global__ __launch_bounds__(NW * 64) void k_step_update(const TX* __restrict__ X, int64_t ld,
                                                          int64_t d, int64_t b,
                                                          const int32_t* __restrict__ idx,
@@ -886,6 +927,9 @@ __global__ __launch_bounds__(NW * 64) void k_step_update(const TX* __restrict__ 
   __shared__ double slots[NW * NTW * 256];
   __shared__ int sidx[KS];
   __shared__ double vs[DEFL ? 64 * 16 * NTW : 1];
+  constexpr bool TURN = sizeof(TX) < 8;
+  constexpr int XTP = 20;
+  __shared__ __align__(16) float xtr[TURN ? NW : 1][2][TURN ? 16 * XTP : 4];
   const int t = threadIdx.x, wave = t / 64, l = t % 64;
   const int lm = l % 16, q = l / 16;
   // Workgroups go to the 8 XCDs in turn; the grid (a multiple of 8 tiles) is
@@ -930,8 +974,12 @@ __global__ __launch_bounds__(NW * 64) void k_step_update(const TX* __restrict__ 
   // wave-uniform branch.
   const int* __restrict__ sq = sidx + 4 * q;
   const double* __restrict__ cq = C + (int64_t)(4 * q) * PC + nt0 * 16 + lm;
+  const int lj = l >> 2, lr = 4 * (l & 3);   // this lane's sample and first row in a block
+  const int64_t rr = r0 + lr;
+  const int64_t rl = VEC && rr + 4 > d ? d - 4 : rr;
   struct Stage {
-    TX x[G][4];
+    float4 xv[TURN ? G : 1];
+    TX x[TURN ? 1 : G][4];
     double nv[G][4][NTW];
   };
   auto load = [&](Stage& S, int64_t g) {
@@ -940,36 +988,63 @@ __global__ __launch_bounds__(NW * 64) void k_step_update(const TX* __restrict__ 
       const int64_t blk = min(g + i, b1 - 1);
       const int* __restrict__ si = sq + blk * 16;
       const double* __restrict__ ci = cq + blk * 16 * PC;
+      if constexpr (TURN) S.xv[i] = col4<TX, VEC>(X + (int64_t)sidx[blk * 16 + lj] * ld, rl, d);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        S.x[i][s] = xrow[(int64_t)si[s] * ld];
+        if constexpr (!TURN) S.x[i][s] = xrow[(int64_t)si[s] * ld];
 #pragma unroll
         for (int u = 0; u < NTW; ++u) S.nv[i][s][u] = ci[s * PC + u * 16];
       }
     }
   };
-  auto compute = [&](const Stage& S, int64_t g) {
+  auto compute = [&](const Stage& S, int64_t g, bool checked) {
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      if (g + i >= b1) break;
+      if (checked && g + i >= b1) break;
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (TURN) {
+        float* __restrict__ wt = xtr[wave][(g + i) & 1];
+        wt[(lr + 0) * XTP + lj] = S.xv[i].x;
+        wt[(lr + 1) * XTP + lj] = S.xv[i].y;
+        wt[(lr + 2) * XTP + lj] = S.xv[i].z;
+        wt[(lr + 3) * XTP + lj] = S.xv[i].w;
+        wave_sync();
+        a = *reinterpret_cast<const float4*>(wt + lm * XTP + 4 * q);
+        wave_sync();
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const double xa = ldx(&S.x[i][s], 0);
+        double xa;
+        if constexpr (TURN)
+          xa = (double)f4at(a, s);
+        else
+          xa = ldx(&S.x[i][s], 0);
 #pragma unroll
         for (int u = 0; u < NTW; ++u) acc[u] = mfma_f64(xa, S.nv[i][s][u], acc[u]);
       }
     }
   };
   if (b0 < b1) {
+    // whole pairs of stages first, with no branch between a stage's loads and
+    // the work before its use (a guarded use lets the compiler move the loads
+    // down to it, and the next stage's loads no longer overlap)
     Stage A, B;
     load(A, b0);
-    for (int64_t g = b0; g < b1; g += 2 * G) {
+    int64_t g = b0;
+    for (; g + 2 * G <= b1; g += 2 * G) {
       load(B, g + G);
       __builtin_amdgcn_sched_barrier(0);
-      compute(A, g);
+      compute(A, g, false);
       load(A, g + 2 * G);
       __builtin_amdgcn_sched_barrier(0);
-      compute(B, g + G);
+      compute(B, g + G, false);
+    }
+    if (g < b1) {
+      compute(A, g, true);
+      if (g + G < b1) {
+        load(B, g + G);
+        compute(B, g + G, true);
+      }
     }
   }
   waves_to_lds<NW, NTW>(red, slots, acc, q, lm);
@@ -1739,14 +1814,29 @@ hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, con
   // row tile, but twice the workgroups, which this latency-bound step needs
   dim3 grid((unsigned)(((X.d + 15) / 16 + 7) / 8 * 8), (unsigned)((p + 15) / 16));
   // waves split the samples: as many as give each about one prefetch group
+  // FP32 / BF16 X in pieces of 4 rows: aligned columns, d a multiple of 4
+  const bool vec = X.dt != 0 && X.ld % 4 == 0 && X.d % 4 == 0 &&
+                   (uintptr_t)X.v % (X.dt == 1 ? 16 : 8) == 0;
+#define LR_UPDATE_V(NWV, GV, KSV, DF, VC)                                                       \
+  launch(k_step_update<TX, NWV, GV, 16 * NTV, 1, KSV, DF, VC>, grid, dim3(NWV * 64), st, pr,   \
+         (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta, df)
 #define LR_UPDATE(NWV, GV, KSV)                                                                \
   LR_DISPATCH_DT(X.dt, TX, LR_DISPATCH_NT(p, NTV, {                                            \
-    if (defl)                                                                                  \
-      launch(k_step_update<TX, NWV, GV, 16 * NTV, 1, KSV, true>, grid, dim3(NWV * 64), st, pr, \
-             (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta, df);                    \
-    else                                                                                       \
-      launch(k_step_update<TX, NWV, GV, 16 * NTV, 1, KSV>, grid, dim3(NWV * 64), st, pr,       \
-             (const TX*)X.v, X.ld, X.d, b, idx, C, p, G, Dl, lam, eta, df);                    \
+    if constexpr (sizeof(TX) < 8) {                                                            \
+      if (defl && vec)                                                                         \
+        LR_UPDATE_V(NWV, GV, KSV, true, true);                                                 \
+      else if (defl)                                                                           \
+        LR_UPDATE_V(NWV, GV, KSV, true, false);                                                \
+      else if (vec)                                                                            \
+        LR_UPDATE_V(NWV, GV, KSV, false, true);                                                \
+      else                                                                                     \
+        LR_UPDATE_V(NWV, GV, KSV, false, false);                                               \
+    } else {                                                                                   \
+      if (defl)                                                                                \
+        LR_UPDATE_V(NWV, GV, KSV, true, false);                                                \
+      else                                                                                     \
+        LR_UPDATE_V(NWV, GV, KSV, false, false);                                               \
+    }                                                                                          \
   }))
   // stage depth (blocks per stage) measured at d = 2048: 2 for small minibatches,
   // 1 for large ones (16 waves each with 2 stages in flight)
@@ -1758,6 +1848,7 @@ hipError_t step_update(const XView& X, int p, int64_t b, const int32_t* idx, con
     LR_UPDATE(16, 1, KSTAGE);
   }
 #undef LR_UPDATE
+#undef LR_UPDATE_V
   return hipGetLastError();
 }
 
