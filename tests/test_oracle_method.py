@@ -2,7 +2,9 @@
 
 * Inner solver: one minibatch step that sees every column once with unit
   weight is exactly a gradient step on F(W) = 1/2 tr W^T B W - tr W^T S (so a
-  dropped term or a wrong sign fails); the solve converges to the direct
+  dropped term or a wrong sign fails); averaged exactly over the sampling
+  distribution the minibatch step is that gradient step (the importance
+  weights make X_B diag(1/(b pi)) X_B^T unbiased for A); the solve converges to the direct
   solution of (lambda I - XX^T) W = S (Theorem "svrgSolve"); a shift below
   lambda_1 is detected.
 * Subspace iteration with exact solves converges at the rate
@@ -54,6 +56,38 @@ def test_svrg_step_full_batch_is_gradient_step():
     got = svrg_step(X, W, Wt, G, lam, eta, np.arange(n), np.ones(n))
     want = W - eta * (B @ W - S)
     assert np.linalg.norm(got - want) < 1e-12 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("b", [1, 2])
+def test_svrg_step_expectation_is_gradient_step(b):
+    """Averaged exactly over the sampling distribution (every ordered b-tuple of
+    i.i.d. draws from pi_i = q_i / Q of the quantised table, weights 1/(b pi_i)),
+    the minibatch step equals the full gradient step W - eta (B W - S): the
+    sampled X_B diag(1/(b pi)) X_B^T is an unbiased estimate of A = XX^T
+    (Section 2.3).  A wrong weight, a missing 1/b or a dropped term fails."""
+    import itertools
+    rng = np.random.default_rng(3)
+    d, n, p = 6, 9, 2
+    X = rng.standard_normal((d, n)) * rng.uniform(0.3, 2.0, size=n)[None, :]
+    X[:, 4] = 0.0   # a zero column: weight 0, never drawn
+    S = rng.standard_normal((d, p))
+    lam = 1.4 * np.linalg.norm(X, 2) ** 2
+    B = lam * np.eye(d) - X @ X.T
+    Wt = rng.standard_normal((d, p))
+    W = Wt + 0.2 * rng.standard_normal((d, p))
+    G = B @ Wt - S
+    eta = 0.3 / lam
+    q, qc = build_table(column_sq_norms(X))
+    pi = q.astype(np.float64) / float(qc[n])
+    cols = [i for i in range(n) if q[i] > 0]
+    assert 4 not in cols
+    mean = np.zeros_like(W)
+    for tup in itertools.product(cols, repeat=b):
+        idx = np.array(tup)
+        prob = float(np.prod(pi[idx]))
+        mean += prob * svrg_step(X, W, Wt, G, lam, eta, idx, 1.0 / (b * pi[idx]))
+    want = W - eta * (B @ W - S)
+    assert np.linalg.norm(mean - want) < 1e-12 * np.linalg.norm(want)
 
 
 def test_svrg_solve_matches_direct_solve():
