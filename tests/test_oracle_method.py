@@ -4,9 +4,9 @@
   weight is exactly a gradient step on F(W) = 1/2 tr W^T B W - tr W^T S (so a
   dropped term or a wrong sign fails); averaged exactly over the sampling
   distribution the minibatch step is that gradient step (the importance
-  weights make X_B diag(1/(b pi)) X_B^T unbiased for A); the solve converges to the direct
-  solution of (lambda I - XX^T) W = S (Theorem "svrgSolve"); a shift below
-  lambda_1 is detected.
+  weights make X_B diag(1/(b pi)) X_B^T unbiased for A); the solve converges
+  to the direct solution of (lambda I - XX^T) W = S (Theorem "svrgSolve"); a
+  shift below lambda_1 is detected.
 * Subspace iteration with exact solves converges at the rate
   (lambda - lambda_k)/(lambda - lambda_{p+1}) (Theorem "zhang" applied to
   C = (lambda I - A)^{-1}).
